@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-cluster RANSAC velocity/heading estimator on one MI355X.
+
+A step is one full estimate of one synthetic frame (prep, hypotheses, scoring,
+refit) with the frame already resident in HBM.  Default workload: the dense
+frame (4096 clusters, log-uniform sizes in [8, 4096] points, 30 % outliers,
+1024 hypotheses per cluster, tau = 0.15 m/s).
+
+Prints one JSON line: throughput in hypothesis-point evaluations per second
+(value), clusters/s, p50/p99 frame latency (host pinned memory -> results in
+host memory), the roofline of the scoring kernel from HIP events recorded
+around it during the timed steps, and the FP64 CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "clusters/s + hyp-point evals/s (% FP32 VALU peak); p50/p99 frame latency"
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 x 2 x 2.4 GHz
+FLOP_PER_EVAL = 4                # two fused multiply-adds per hypothesis-point residual
+
+WORKLOAD_TEXT = {
+    "dense": ("dense frame: 4096 clusters, log-uniform [8, 4096] points (theta U[-60,60] deg, "
+              "(vx, vy) U[-30,30]^2 m/s, noise sigma 0.05 m/s), 30% outliers (15% uniform "
+              "U[-40,40], 15% micro-Doppler band +/-[0.5,2]|v|), 1024 hypotheses, tau 0.15 m/s, FP32"),
+    "small": ("small frame: 64 clusters of U{20..200} points, 20% uniform outliers, "
+              "256 hypotheses, tau 0.15 m/s, FP32"),
+}
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="dense", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--latency-frames", type=int, default=200,
+                    help="frames timed from pinned host memory to results in host memory")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: min(16, cpus))")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this estimator runs on one GPU (asked for --gpus {args.gpus}); clusters are "
+              "independent, so a multi-GPU deployment shards frames or clusters without any "
+              "collective and its throughput is the sum of single-GPU runs.", file=sys.stderr)
+        return 2
+    if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
+        print("bench.py: run on a single rank", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2012_12618_amd import binding, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    binding.load_library()
+    dev = torch.device("cuda:0")
+    name = args.workload
+    print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)
+    frame, n_hyp, tau = synth.make_workload(name)
+    K, N = frame.n_clusters, frame.n_points
+    evals = synth.evals_per_frame(frame.offsets, n_hyp)
+
+    theta = torch.from_numpy(frame.theta).to(dev)
+    vd = torch.from_numpy(frame.vd).to(dev)
+    offsets = torch.from_numpy(frame.offsets).to(dev)
+    out = binding.allocate_outputs(K, N, n_hyp, dev, want_near=True)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(i):
+        binding.rv_estimate_velocity(theta, vd, offsets, n_hyp, tau, synth.ransac_seed(name, i),
+                                     out=out, stream=stream)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    # Timed region: K steps between events on the launch stream; the library's
+    # own events around each kernel give per-kernel durations.
+    binding.rv_stage_times()  # drop anything recorded before
+    binding.rv_stage_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    binding.rv_stage_timing(False)
+    stage_ms, n_calls = binding.rv_stage_times()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    sec = ms_per_step / 1e3
+    evals_per_s = evals / sec
+    clusters_per_s = K / sec
+    stage_avg = [x / max(n_calls, 1) for x in stage_ms]
+    score_ms = stage_avg[2]
+    achieved_tflops = FLOP_PER_EVAL * evals / (score_ms / 1e3) / 1e12
+
+    # Frame latency: pinned host frame -> device -> estimate -> results in host memory.
+    print(f"[bench] latency over {args.latency_frames} frames", file=sys.stderr, flush=True)
+    frames = [frame] + [synth.make_frame(synth.WORKLOADS[name][0], 1000 + f) for f in range(3)]
+    slots = []
+    for f in frames:
+        h = tuple(torch.from_numpy(a).pin_memory() for a in (f.theta, f.vd, f.offsets))
+        d = tuple(torch.empty(a.shape, dtype=a.dtype, device=dev) for a in h)
+        o = binding.allocate_outputs(f.n_clusters, f.n_points, n_hyp, dev, want_near=True)
+        r = {k: torch.empty(o[k].shape, dtype=o[k].dtype).pin_memory()
+             for k in ("vx", "vy", "heading", "n_inliers", "status")}
+        slots.append((h, d, o, r))
+    lat = []
+    for i in range(args.latency_frames):
+        (h_t, h_v, h_o), (d_t, d_v, d_o), o2, r = slots[i % len(slots)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d_t.copy_(h_t, non_blocking=True)
+        d_v.copy_(h_v, non_blocking=True)
+        d_o.copy_(h_o, non_blocking=True)
+        binding.rv_estimate_velocity(d_t, d_v, d_o, n_hyp, tau, synth.ransac_seed(name, 10_000 + i),
+                                     out=o2, stream=stream)
+        for k, hbuf in r.items():
+            hbuf.copy_(o2[k], non_blocking=True)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    del slots
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        print(f"[bench] oracle on the host, {threads} threads", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        oracle.estimate_velocity(frame.theta, frame.vd, frame.offsets, n_hyp, tau,
+                                 synth.ransac_seed(name, 0), want_mask=False, n_threads=threads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": evals / dt, "unit": "hyp-point evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"one whole {name} frame ({K} clusters, {evals} evals), FP64, {dt:.2f} s wall",
+               "clusters_per_s": K / dt}
+
+    line = {
+        "metric": METRIC,
+        "value": evals_per_s,
+        "unit": "hyp-point evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[name], "clusters": K, "points": N, "n_hyp": n_hyp,
+                   "tau": tau, "evals_per_frame": evals},
+        "clusters_per_s": clusters_per_s,
+        "frac_fp32_valu_peak": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+        "latency_ms": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "frames": len(lat),
+                       "scope": "pinned host frame -> H2D -> estimate -> D2H of per-cluster results"},
+        "stage_ms": dict(zip(binding.STAGE_NAMES, stage_avg)),
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "roofline": {"bound": "alu", "kernel": "score_kernel", "achieved": achieved_tflops,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic_flop_per_launch": FLOP_PER_EVAL * evals,
+                     "kernel_ms": score_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,140 @@
+/*
+ * rv.h -- C ABI of the MI355X (gfx950) per-cluster velocity and heading
+ * estimator of "Parallelized Instantaneous Velocity and Heading Estimation of
+ * Objects using Single Imaging Radar" (Singh, Sil, Sharma).
+ *
+ * For every cluster of radar points the library
+ *   1. runs RANSAC over the rigid-body velocity profile of Sec. 3.2, Eq. 6,
+ *        v_d = vx cos(theta) + vy sin(theta):
+ *      each hypothesis draws a pair of seed points, solves the 2x2 system for
+ *      (vx, vy), and counts the points with |v_d - vx cos - vy sin| < tau
+ *      (Sec. 3.1, Alg. 1, as the velocity-profile variant);
+ *   2. keeps the hypothesis with the most inliers (Sec. 3.1; ties: lowest index);
+ *   3. refits (vx, vy) by least squares on that hypothesis's inliers
+ *      (Sec. 3.2, Eq. 7, Alg. 2: the pseudoinverse solution);
+ *   4. reports heading = atan2(vy, vx) (Eq. 8, quadrant-correct).
+ *
+ * Memory and streams.  Every array argument of rv_estimate_velocity is a
+ * DEVICE pointer owned by the caller; the library allocates nothing, keeps no
+ * pointer after the call returns, and enqueues its work asynchronously on
+ * `stream` (a hipStream_t; NULL is the default stream).  Results are valid
+ * once the caller has synchronised that stream.  Calls that share a workspace
+ * must be ordered on one stream.
+ *
+ * Errors.  Argument checks run on the host before anything is enqueued; a
+ * negative rv_status_t means nothing was launched, and rv_last_error() returns
+ * a message (thread-local).  Per-cluster conditions are not errors: they set
+ * that cluster's status byte and NaN outputs, and the call returns RV_OK.
+ */
+#ifndef RV_H
+#define RV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RV_OK = 0,
+    RV_ERR_INVALID_ARG = -1, /* null pointer, bad size or scalar */
+    RV_ERR_WORKSPACE = -2,   /* workspace missing or smaller than rv_workspace_bytes() */
+    RV_ERR_HIP = -3          /* a HIP launch failed; rv_last_error() has the HIP message */
+} rv_status_t;
+
+/* Per-cluster status byte. */
+enum {
+    RV_CLUSTER_OK = 0,
+    RV_CLUSTER_TOO_FEW_POINTS = 1, /* fewer than two points */
+    RV_CLUSTER_ALL_DEGENERATE = 2, /* no valid seed pair among the n_hyp draws */
+    RV_CLUSTER_SINGULAR_REFIT = 3, /* the kept inlier set has fewer than two points
+                                      or a non-positive normal-equation determinant */
+    RV_CLUSTER_BAD_OFFSETS = 4     /* offsets[k] < 0, offsets[k+1] < offsets[k], or
+                                      offsets[k+1] > n_points */
+};
+
+/* A seed pair is degenerate (its hypothesis invalid) when its two azimuths,
+   promoted to double, differ by less than this many radians. */
+#define RV_MIN_SEED_SEPARATION 1e-3
+/* Half-width (m/s) of the "near tau" window counted in n_near_tau. */
+#define RV_NEAR_TAU_WINDOW 1e-5
+/* Largest accepted n_hyp. */
+#define RV_MAX_HYP (1 << 20)
+
+/*
+ * Bytes of device workspace rv_estimate_velocity needs for these sizes
+ * (a pure host computation; 0 for negative sizes).
+ */
+size_t rv_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t n_hyp);
+
+/*
+ * Estimate vx, vy (m/s) and heading (rad) of every cluster of one CSR frame.
+ *
+ * Inputs (device, read only):
+ *   theta[n_points]   azimuth of each point, radians, float32.  Measured from
+ *                     the +x (longitudinal) axis, counter-clockwise positive.
+ *   vd[n_points]      radial Doppler velocity of each point, m/s, float32.
+ *   cluster_offsets[n_clusters + 1]  int32; the points of cluster k are
+ *                     [offsets[k], offsets[k+1]).  Expected: offsets[0] = 0,
+ *                     non-decreasing, offsets[n_clusters] = n_points; a cluster
+ *                     whose bounds are inconsistent gets RV_CLUSTER_BAD_OFFSETS
+ *                     and no memory outside [0, n_points) is touched.
+ * Scalars:
+ *   n_clusters >= 0, 0 <= n_points <= INT32_MAX.
+ *   n_hyp in [1, RV_MAX_HYP]: hypotheses per cluster (the paper's max_trials).
+ *   tau > 0 and finite: a point is an inlier when |residual| < tau (strict).
+ *   seed: hypothesis h of cluster k draws its pair from Philox4x32-10 with
+ *     key = (seed & 0xffffffff, seed >> 32) and counter = (h, k, 0, 0), so a
+ *     cluster's result depends only on (seed, k, its points, n_hyp, tau).
+ * Outputs (device, written; [n_clusters] each):
+ *   vx, vy, heading (float32; NaN when status != RV_CLUSTER_OK),
+ *   n_inliers (int32; size of the refit set), status (uint8, RV_CLUSTER_*).
+ * Optional outputs (device, may be NULL):
+ *   n_near_tau[n_clusters]   int32: points of the kept hypothesis whose double-
+ *                            precision |residual| is within RV_NEAR_TAU_WINDOW of tau.
+ *   inlier_bits[ceil(n_points/32)]  uint32: the frame-wide inlier mask (Sec. 3.1:
+ *                            logical OR of the per-cluster masks); bit p%32 of word
+ *                            p/32 is point p.  Cleared by the call.
+ *   hyp_counts[n_clusters * n_hyp]  int32: float32-stage inlier count of every
+ *                            hypothesis (0 for invalid ones), cluster-major.
+ *   best_hyp[n_clusters]     int32: index of the kept hypothesis, -1 if none.
+ * Workspace: device memory of at least rv_workspace_bytes(n_clusters, n_points,
+ *   n_hyp) bytes, 256-byte aligned; contents need no initialisation.
+ * Returns RV_OK or a negative rv_status_t.
+ */
+int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                         int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau,
+                         uint64_t seed, float *vx, float *vy, float *heading, int32_t *n_inliers,
+                         uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                         int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *rv_last_error(void);
+
+/*
+ * Instrumentation (not part of the estimate).  While enabled, every
+ * rv_estimate_velocity call records HIP events around each of its kernels on
+ * its stream.  rv_stage_times waits for the recorded events, writes the summed
+ * milliseconds per stage (prep, hypotheses, scoring, refit) into ms[0..3],
+ * the number of calls into *n_calls, and clears the record.  Returns RV_OK or
+ * RV_ERR_HIP.
+ */
+int rv_stage_timing(int enable);
+int rv_stage_times(double *ms, int64_t *n_calls);
+
+/*
+ * Test hook: n independent Philox4x32-10 blocks computed on the GPU by the same
+ * device function the estimator uses.  ctr[4n], key[2n], out[4n] are device
+ * arrays of uint32 (block t uses ctr[4t..4t+3] and key[2t..2t+1]).  Enqueued on
+ * `stream`.  Returns RV_OK or a negative rv_status_t.
+ */
+int rv_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
+                     void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RV_H */

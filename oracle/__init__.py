@@ -72,6 +72,9 @@ def _load():
     lib.oracle_map_pair.argtypes = [ctypes.c_uint32, ctypes.c_uint32, i64, P, P]
     lib.oracle_draw_pair.restype = None
     lib.oracle_draw_pair.argtypes = [u64, ctypes.c_uint32, ctypes.c_uint32, i64, P, P]
+    lib.oracle_fit_hypothesis.restype = ctypes.c_int
+    lib.oracle_fit_hypothesis.argtypes = [P, P, P, i64, i64, f32, u64, i64, i64, f64,
+                                          P, P, P, P, P, P, P, P]
     lib.oracle_all_pairs_best.restype = i32
     lib.oracle_all_pairs_best.argtypes = [P, P, i32, f32, P, P]
     _lib = lib
@@ -181,6 +184,44 @@ def estimate_velocity(theta, vd, offsets, n_hyp: int, tau: float, seed: int, *,
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return out
+
+
+@dataclass
+class HypothesisFit:
+    vx: float
+    vy: float
+    heading: float
+    n_inliers: int
+    n_near_tau: int
+    status: int
+    mask: np.ndarray       # uint8 [n_k], inlier set of the cluster's points
+    near_mask: np.ndarray  # uint8 [n_k], points within near_window of tau
+
+
+def fit_hypothesis(theta, vd, offsets, tau: float, seed: int, k: int, h: int, *,
+                   near_window: float = NEAR_TAU_WINDOW) -> HypothesisFit | None:
+    """Refit of cluster k on the inliers of its hypothesis h (None if h is degenerate)."""
+    lib = _load()
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    v = np.ascontiguousarray(vd, dtype=np.float32)
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    n = int(off[k + 1]) - int(off[k])
+    mask = np.zeros(max(n, 1), dtype=np.uint8)
+    near = np.zeros(max(n, 1), dtype=np.uint8)
+    vx, vy, hd = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n_in, n_near = ctypes.c_int32(), ctypes.c_int32()
+    st = ctypes.c_uint8()
+    rc = lib.oracle_fit_hypothesis(
+        _ptr(th), _ptr(v), _ptr(off), off.shape[0] - 1, th.shape[0], float(tau),
+        int(seed) & 0xFFFFFFFFFFFFFFFF, int(k), int(h), near_window,
+        ctypes.byref(vx), ctypes.byref(vy), ctypes.byref(hd), ctypes.byref(n_in),
+        ctypes.byref(n_near), ctypes.byref(st), _ptr(mask), _ptr(near))
+    if rc == -2:
+        return None
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return HypothesisFit(vx.value, vy.value, hd.value, n_in.value, n_near.value, st.value,
+                         mask[:n], near[:n])
 
 
 def all_pairs_best(theta, vd, tau: float):

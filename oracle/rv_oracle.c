@@ -172,6 +172,64 @@ static int cluster_bounds(const struct job *J, int64_t k, int64_t *lo, int64_t *
     return 1;
 }
 
+/* Result of the least-squares refit of one cluster. */
+struct fit {
+    double vx, vy, heading;
+    int32_t n_inliers, n_near;
+    uint8_t status;
+};
+
+/*
+ * Least-squares refit on the inliers of hypothesis (hvx, hvy) (Sec. 3.2,
+ * Eq. 7, Alg. 2): every finite point with |v_d - hvx cos - hvy sin| < tau
+ * joins the inlier set, the normal equations (A^T A) v = A^T v_d are summed
+ * over it and solved, and the heading is atan2(vy, vx) (Eq. 8).  mask and
+ * near_mask (n bytes each, nullable) receive the inlier set and the points
+ * within near_window of tau.
+ */
+static void refit(const float *vd, const double *c, const double *s, const uint8_t *ok,
+                  int64_t n, double hvx, double hvy, double tau, double near_window,
+                  uint8_t *mask, uint8_t *near_mask, struct fit *f)
+{
+    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
+    int64_t n_in = 0, n_near = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        if (mask) mask[p] = 0;
+        if (near_mask) near_mask[p] = 0;
+        if (!ok[p])
+            continue;
+        double v = (double)vd[p];
+        double res = fabs(v - hvx * c[p] - hvy * s[p]);
+        if (fabs(res - tau) <= near_window) {
+            n_near += 1;
+            if (near_mask) near_mask[p] = 1;
+        }
+        if (!(res < tau))
+            continue;
+        n_in += 1;
+        if (mask) mask[p] = 1;
+        scc += c[p] * c[p];
+        scs += c[p] * s[p];
+        sss += s[p] * s[p];
+        scv += c[p] * v;
+        ssv += s[p] * v;
+    }
+    f->n_inliers = (int32_t)n_in;
+    f->n_near = (int32_t)n_near;
+    double det = scc * sss - scs * scs;
+    if (n_in < 2 || !(det > 0.0)) {
+        f->vx = NAN;
+        f->vy = NAN;
+        f->heading = NAN;
+        f->status = OR_CLUSTER_SINGULAR_REFIT;
+        return;
+    }
+    f->vx = (sss * scv - scs * ssv) / det;
+    f->vy = (scc * ssv - scs * scv) / det;
+    f->heading = atan2(f->vy, f->vx);
+    f->status = OR_CLUSTER_OK;
+}
+
 static void estimate_cluster(struct job *J, int64_t r, double *c, double *s, uint8_t *ok)
 {
     int64_t k = cluster_of(J, r);
@@ -276,45 +334,15 @@ static void estimate_cluster(struct job *J, int64_t r, double *c, double *s, uin
         return;
     }
 
-    /* Least-squares refit on the kept hypothesis's inliers (Eq. 7, Alg. 2):
-     * the normal equations (A^T A) v = A^T v_r over the inlier rows. */
-    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
-    int64_t n_in = 0, n_near = 0;
-    for (int64_t p = 0; p < n; ++p) {
-        if (!ok[p])
-            continue;
-        double v = (double)vd[p];
-        double res = fabs(v - best_vx * c[p] - best_vy * s[p]);
-        if (fabs(res - tau) <= J->near_window)
-            n_near += 1;
-        if (!(res < tau))
-            continue;
-        n_in += 1;
-        if (J->inlier_mask)
-            J->inlier_mask[lo + p] = 1;
-        scc += c[p] * c[p];
-        scs += c[p] * s[p];
-        sss += s[p] * s[p];
-        scv += c[p] * v;
-        ssv += s[p] * v;
-    }
-    J->n_inliers[r] = (int32_t)n_in;
-    if (J->n_near_tau) J->n_near_tau[r] = (int32_t)n_near;
-
-    double det = scc * sss - scs * scs;
-    if (n_in < 2 || !(det > 0.0)) {
-        J->vx[r] = NAN;
-        J->vy[r] = NAN;
-        J->heading[r] = NAN;
-        J->status[r] = OR_CLUSTER_SINGULAR_REFIT;
-        return;
-    }
-    double fvx = (sss * scv - scs * ssv) / det;
-    double fvy = (scc * ssv - scs * scv) / det;
-    J->vx[r] = fvx;
-    J->vy[r] = fvy;
-    J->heading[r] = atan2(fvy, fvx);  /* Eq. 8 */
-    J->status[r] = OR_CLUSTER_OK;
+    struct fit f;
+    refit(J->vd + lo, c, s, ok, n, best_vx, best_vy, tau, J->near_window,
+          J->inlier_mask ? J->inlier_mask + lo : NULL, NULL, &f);
+    J->vx[r] = f.vx;
+    J->vy[r] = f.vy;
+    J->heading[r] = f.heading;
+    J->n_inliers[r] = f.n_inliers;
+    J->status[r] = f.status;
+    if (J->n_near_tau) J->n_near_tau[r] = f.n_near;
 }
 
 static int64_t cluster_size(const struct job *J, int64_t r)
@@ -489,4 +517,56 @@ int32_t oracle_all_pairs_best(const float *theta, const float *vd, int32_t n, fl
     }
     free(c); free(s); free(ok);
     return best;
+}
+
+/*
+ * The steps after selection for a given hypothesis h of cluster k: its seed
+ * pair and 2x2 solve, then the refit on its inliers.  Used to check a result
+ * built on another hypothesis than the oracle's own choice.  mask and
+ * near_mask have one byte per point of the cluster (nullable).  Returns 0, -1
+ * for invalid arguments, or -2 when hypothesis h is degenerate.
+ */
+int oracle_fit_hypothesis(const float *theta, const float *vd, const int32_t *offsets,
+                          int64_t n_clusters, int64_t n_points, float tau, uint64_t seed,
+                          int64_t k, int64_t h, double near_window, double *vx, double *vy,
+                          double *heading, int32_t *n_inliers, int32_t *n_near, uint8_t *status,
+                          uint8_t *mask, uint8_t *near_mask)
+{
+    if (k < 0 || k >= n_clusters || h < 0 || h > 0xFFFFFFFFLL || !(tau > 0.0f))
+        return -1;
+    int64_t lo = offsets[k], hi = offsets[k + 1];
+    if (lo < 0 || hi < lo || hi > n_points || hi - lo < 2)
+        return -1;
+    int64_t n = hi - lo;
+    const float *th = theta + lo;
+    const float *v = vd + lo;
+    double *c = (double *)malloc((size_t)n * sizeof(double));
+    double *s = (double *)malloc((size_t)n * sizeof(double));
+    uint8_t *ok = (uint8_t *)malloc((size_t)n);
+    for (int64_t p = 0; p < n; ++p) {
+        c[p] = cos((double)th[p]);
+        s[p] = sin((double)th[p]);
+        ok[p] = isfinite(th[p]) && isfinite(v[p]);
+    }
+    int64_t i, j;
+    oracle_draw_pair(seed, (uint32_t)h, (uint32_t)k, n, &i, &j);
+    int rc = 0;
+    if (!(ok[i] && ok[j] && fabs((double)th[j] - (double)th[i]) >= MIN_SEED_SEPARATION)) {
+        rc = -2;
+    } else {
+        double vi = (double)v[i], vj = (double)v[j];
+        double det = c[i] * s[j] - s[i] * c[j];
+        double hvx = (vi * s[j] - vj * s[i]) / det;
+        double hvy = (c[i] * vj - c[j] * vi) / det;
+        struct fit f;
+        refit(v, c, s, ok, n, hvx, hvy, (double)tau, near_window, mask, near_mask, &f);
+        *vx = f.vx;
+        *vy = f.vy;
+        *heading = f.heading;
+        *n_inliers = f.n_inliers;
+        *n_near = f.n_near;
+        *status = f.status;
+    }
+    free(c); free(s); free(ok);
+    return rc;
 }

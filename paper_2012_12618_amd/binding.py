@@ -1,0 +1,204 @@
+"""Thin ctypes binding of ``librv.so`` (include/rv.h): argument marshalling only.
+
+PyTorch supplies device memory and the stream; every step of the estimate runs
+in the library's HIP kernels.  The library must be built (``build.py``); if it
+is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "librv.so")
+
+RV_OK = 0
+RV_ERR_INVALID_ARG = -1
+RV_ERR_WORKSPACE = -2
+RV_ERR_HIP = -3
+
+RV_CLUSTER_OK = 0
+RV_CLUSTER_TOO_FEW_POINTS = 1
+RV_CLUSTER_ALL_DEGENERATE = 2
+RV_CLUSTER_SINGULAR_REFIT = 3
+RV_CLUSTER_BAD_OFFSETS = 4
+
+RV_MIN_SEED_SEPARATION = 1e-3
+RV_NEAR_TAU_WINDOW = 1e-5
+RV_MAX_HYP = 1 << 20
+
+N_STAGES = 4
+STAGE_NAMES = ("prep", "hyp", "score", "refit")
+
+_lib = None
+
+
+class RVError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"rv error {code}: {message}")
+        self.code = code
+
+
+def load_library() -> ctypes.CDLL:
+    """Load librv.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"HIP library not built: {LIB_PATH} is missing "
+            "(run `python -m paper_2012_12618_amd.build` or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    lib.rv_workspace_bytes.restype = ctypes.c_size_t
+    lib.rv_workspace_bytes.argtypes = [i64, i64, i32]
+    lib.rv_estimate_velocity.restype = ctypes.c_int
+    lib.rv_estimate_velocity.argtypes = [
+        P, P, P, i64, i64, i32, ctypes.c_float, ctypes.c_uint64,
+        P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P,
+    ]
+    lib.rv_last_error.restype = ctypes.c_char_p
+    lib.rv_last_error.argtypes = []
+    lib.rv_stage_timing.restype = ctypes.c_int
+    lib.rv_stage_timing.argtypes = [ctypes.c_int]
+    lib.rv_stage_times.restype = ctypes.c_int
+    lib.rv_stage_times.argtypes = [P, P]
+    lib.rv_philox4x32_10.restype = ctypes.c_int
+    lib.rv_philox4x32_10.argtypes = [P, P, P, i64, P]
+    _lib = lib
+    return lib
+
+
+def rv_last_error() -> str:
+    return load_library().rv_last_error().decode()
+
+
+def _check(code: int) -> None:
+    if code != RV_OK:
+        raise RVError(code, rv_last_error())
+
+
+def rv_workspace_bytes(n_clusters: int, n_points: int, n_hyp: int) -> int:
+    return int(load_library().rv_workspace_bytes(int(n_clusters), int(n_points), int(n_hyp)))
+
+
+def _dev_ptr(t: torch.Tensor | None, dtype: torch.dtype, device: torch.device, name: str):
+    if t is None:
+        return None
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
+
+
+def allocate_outputs(n_clusters: int, n_points: int, n_hyp: int, device, *,
+                     want_near: bool = True, want_bits: bool = False, debug: bool = False) -> dict:
+    """Output tensors for rv_estimate_velocity (plus the workspace)."""
+    dev = torch.device(device)
+    out = {
+        "vx": torch.empty(n_clusters, dtype=torch.float32, device=dev),
+        "vy": torch.empty(n_clusters, dtype=torch.float32, device=dev),
+        "heading": torch.empty(n_clusters, dtype=torch.float32, device=dev),
+        "n_inliers": torch.empty(n_clusters, dtype=torch.int32, device=dev),
+        "status": torch.empty(n_clusters, dtype=torch.uint8, device=dev),
+        "workspace": torch.empty(max(rv_workspace_bytes(n_clusters, n_points, n_hyp), 1),
+                                 dtype=torch.uint8, device=dev),
+    }
+    if want_near:
+        out["n_near_tau"] = torch.empty(n_clusters, dtype=torch.int32, device=dev)
+    if want_bits:
+        out["inlier_bits"] = torch.empty((n_points + 31) // 32, dtype=torch.int32, device=dev)
+    if debug:
+        out["hyp_counts"] = torch.empty(n_clusters * n_hyp, dtype=torch.int32, device=dev)
+        out["best_hyp"] = torch.empty(n_clusters, dtype=torch.int32, device=dev)
+    return out
+
+
+def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
+                         n_hyp: int, tau: float, seed: int, *, want_near: bool = True,
+                         want_bits: bool = False, debug: bool = False, out: dict | None = None,
+                         stream: torch.cuda.Stream | None = None, validate: bool = False) -> dict:
+    """Per-cluster (vx, vy, heading, n_inliers, status) of one CSR frame.
+
+    ``theta``/``vd``: float32 [N] on a GPU; ``offsets``: int32 [K+1] on the same
+    device.  Outputs (and the workspace) are allocated with torch unless ``out``
+    (from ``allocate_outputs``) is given.  Work is enqueued on ``stream`` (default:
+    torch's current stream); the returned tensors are ready after that stream
+    synchronises.  ``validate`` checks the offsets on the host first (a device
+    to host copy; off by default).  Returned dict keys: vx, vy, heading,
+    n_inliers, status and, when requested, n_near_tau, inlier_bits (int32 words,
+    bit p%32 of word p/32 is point p), hyp_counts [K*H], best_hyp.
+    """
+    lib = load_library()
+    device = theta.device
+    if device.type != "cuda":
+        raise ValueError("theta must be a GPU tensor")
+    n_points = int(theta.numel())
+    n_clusters = int(offsets.numel()) - 1
+    if n_clusters < 0:
+        raise ValueError("offsets needs n_clusters + 1 entries")
+    if int(vd.numel()) != n_points:
+        raise ValueError("theta and vd differ in length")
+    if validate:
+        off = offsets.cpu()
+        if off[0] != 0 or off[-1] != n_points or bool((off[1:] < off[:-1]).any()):
+            raise ValueError("offsets must start at 0, be non-decreasing and end at n_points")
+    if out is None:
+        out = allocate_outputs(n_clusters, n_points, n_hyp, device, want_near=want_near,
+                               want_bits=want_bits, debug=debug)
+    ws = out["workspace"]
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    code = lib.rv_estimate_velocity(
+        _dev_ptr(theta, torch.float32, device, "theta"),
+        _dev_ptr(vd, torch.float32, device, "vd"),
+        _dev_ptr(offsets, torch.int32, device, "offsets"),
+        n_clusters, n_points, int(n_hyp), float(tau), int(seed) & 0xFFFFFFFFFFFFFFFF,
+        _dev_ptr(out["vx"], torch.float32, device, "vx"),
+        _dev_ptr(out["vy"], torch.float32, device, "vy"),
+        _dev_ptr(out["heading"], torch.float32, device, "heading"),
+        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
+        _dev_ptr(out["status"], torch.uint8, device, "status"),
+        _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau"),
+        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
+        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
+        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+        ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream),
+    )
+    _check(code)
+    return {k: v for k, v in out.items() if k != "workspace"}
+
+
+def rv_stage_timing(enable: bool) -> None:
+    _check(load_library().rv_stage_timing(1 if enable else 0))
+
+
+def rv_stage_times() -> tuple[list[float], int]:
+    """(summed ms per stage [prep, hyp, score, refit], number of timed calls)."""
+    ms = (ctypes.c_double * N_STAGES)()
+    n = ctypes.c_int64()
+    _check(load_library().rv_stage_times(ms, ctypes.byref(n)))
+    return list(ms), int(n.value)
+
+
+def rv_philox4x32_10(ctr: torch.Tensor, key: torch.Tensor,
+                     stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+    """GPU Philox4x32-10 blocks: ctr int32/uint32 [n, 4], key [n, 2] -> [n, 4] (int32 bits)."""
+    lib = load_library()
+    device = ctr.device
+    n = int(ctr.shape[0])
+    ctr = ctr.contiguous()
+    key = key.contiguous()
+    out = torch.empty((n, 4), dtype=torch.int32, device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    _check(lib.rv_philox4x32_10(ctypes.c_void_p(ctr.data_ptr()), ctypes.c_void_p(key.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), n,
+                                ctypes.c_void_p(stream.cuda_stream)))
+    return out

@@ -1,0 +1,147 @@
+"""GPU-versus-oracle acceptance protocol (helper module for the GPU tests and the
+smoke check; not collected by pytest).
+
+The estimator scores hypotheses in float32 while the oracle works in FP64, so
+the inlier count of a hypothesis may differ where a residual lies within the
+float32 rounding error of tau.  The protocol:
+
+1. status bytes equal;
+2. per hypothesis: the GPU count lies in the oracle's [count_lo, count_hi] band
+   (the band covers the float32 error bound of each residual, and at least
+   1e-5 m/s); an invalid hypothesis counts 0;
+3. selection: when no candidate for the maximum has an ambiguous count the GPU
+   keeps the oracle's hypothesis; otherwise it keeps a candidate (count_hi at
+   least the largest count_lo), reported as an ambiguous selection;
+4. the refit is compared with the oracle's refit of the hypothesis the GPU
+   kept: inlier masks equal except at points flagged within 1e-5 m/s of tau;
+   with equal masks vx, vy agree within 1e-4 m/s; the heading agrees within
+   2e-4/|v| + 1e-6 rad when |v| >= 0.01 m/s.
+"""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+V_TOL = 1e-4
+
+
+def unpack_bits(words: np.ndarray, n_points: int) -> np.ndarray:
+    """int32/uint32 words (bit p%32 of word p/32 = point p) -> bool [n_points]."""
+    w = np.ascontiguousarray(words).view(np.uint32)
+    return np.unpackbits(w.view(np.uint8), bitorder="little")[:n_points].astype(bool)
+
+
+def run_gpu(theta, vd, offsets, n_hyp, tau, seed, *, debug=True, bits=True, device="cuda:0",
+            label=""):
+    """Run the HIP estimator on numpy inputs; returns numpy outputs."""
+    import torch
+
+    from paper_2012_12618_amd import binding
+
+    print(f"[gpu] rv_estimate_velocity {label} K={len(offsets) - 1} N={len(theta)} "
+          f"H={n_hyp} tau={tau} seed={seed:#x}", flush=True)
+    t = torch.from_numpy(np.ascontiguousarray(theta, np.float32)).to(device)
+    v = torch.from_numpy(np.ascontiguousarray(vd, np.float32)).to(device)
+    o = torch.from_numpy(np.ascontiguousarray(offsets, np.int32)).to(device)
+    res = binding.rv_estimate_velocity(t, v, o, n_hyp, tau, seed, want_near=True,
+                                       want_bits=bits, debug=debug)
+    torch.cuda.synchronize()
+    out = {k: x.cpu().numpy() for k, x in res.items()}
+    if bits:
+        out["mask"] = unpack_bits(out["inlier_bits"], len(theta))
+    return out
+
+
+def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True) -> dict:
+    """Apply the protocol to GPU outputs ``g`` and oracle result ``o`` (debug run)."""
+    import oracle
+
+    offsets = np.asarray(offsets, dtype=np.int64)
+    K = len(offsets) - 1
+    stats = {"clusters": K, "ambiguous_selection": 0, "mask_diff_points": 0, "max_dv": 0.0,
+             "max_dheading": 0.0, "hyp_checked": 0}
+    assert np.array_equal(g["status"], o.status), (
+        f"status differs at clusters {np.flatnonzero(g['status'] != o.status)[:10]}")
+    if K == 0:
+        return stats
+
+    H = n_hyp
+    if check_hyp:
+        gc = g["hyp_counts"].reshape(K, H)
+        valid = o.hyp_valid.astype(bool)
+        out_of_band = valid & ((gc < o.hyp_count_lo) | (gc > o.hyp_count_hi))
+        if out_of_band.any():
+            k, h = np.argwhere(out_of_band)[0]
+            raise AssertionError(
+                f"{out_of_band.sum()} hypothesis counts outside the band; first k={k} h={h}: "
+                f"gpu={gc[k, h]} band=[{o.hyp_count_lo[k, h]}, {o.hyp_count_hi[k, h]}] "
+                f"oracle={o.hyp_count[k, h]} vx={o.hyp_vx[k, h]} vy={o.hyp_vy[k, h]}")
+        assert np.all(gc[~valid] == 0), "an invalid hypothesis has a nonzero count"
+        stats["hyp_checked"] = int(valid.sum())
+
+    gmask = g.get("mask")
+    for k in range(K):
+        st = int(o.status[k])
+        if st in (oracle.CLUSTER_TOO_FEW_POINTS, oracle.CLUSTER_BAD_OFFSETS,
+                  oracle.CLUSTER_ALL_DEGENERATE):
+            assert g["n_inliers"][k] == 0
+            assert math.isnan(g["vx"][k]) and math.isnan(g["vy"][k]) and math.isnan(g["heading"][k])
+            assert g["best_hyp"][k] == -1
+            continue
+        lo, hi = int(offsets[k]), int(offsets[k + 1])
+        hg, ho = int(g["best_hyp"][k]), int(o.best_hyp[k])
+        if hg == ho:
+            ref_vx, ref_vy, ref_hd = o.vx[k], o.vy[k], o.heading[k]
+            ref_n, ref_near = int(o.n_inliers[k]), int(o.n_near_tau[k])
+            ref_mask = o.inlier_mask[lo:hi].astype(bool) if o.inlier_mask is not None else None
+            ref_nearmask = None
+            ref_status = st
+        else:
+            assert check_hyp, f"cluster {k}: gpu kept h={hg}, oracle h={ho}"
+            valid = o.hyp_valid[k].astype(bool)
+            clo, chi = o.hyp_count_lo[k], o.hyp_count_hi[k]
+            m_lo = clo[valid].max()
+            cand = valid & (chi >= m_lo)
+            assert (clo[cand] != chi[cand]).any(), (
+                f"cluster {k}: selection differs (gpu {hg}, oracle {ho}) without ambiguity")
+            assert cand[hg], f"cluster {k}: gpu kept h={hg} which cannot be a maximum"
+            stats["ambiguous_selection"] += 1
+            f = oracle.fit_hypothesis(theta, vd, offsets.astype(np.int32), tau, seed, k, hg)
+            assert f is not None
+            ref_vx, ref_vy, ref_hd = f.vx, f.vy, f.heading
+            ref_n, ref_near = f.n_inliers, f.n_near_tau
+            ref_mask, ref_nearmask, ref_status = f.mask.astype(bool), f.near_mask.astype(bool), f.status
+        assert int(g["status"][k]) == ref_status
+        masks_equal = True
+        if gmask is not None and ref_mask is not None:
+            diff = np.flatnonzero(gmask[lo:hi] != ref_mask)
+            if diff.size:
+                if ref_nearmask is None:
+                    f = oracle.fit_hypothesis(theta, vd, offsets.astype(np.int32), tau, seed, k, hg)
+                    ref_nearmask = f.near_mask.astype(bool)
+                assert ref_nearmask[diff].all(), (
+                    f"cluster {k}: inlier masks differ at points not near tau: {diff[:10]}")
+                stats["mask_diff_points"] += int(diff.size)
+                masks_equal = False
+        if masks_equal:
+            assert int(g["n_inliers"][k]) == ref_n, f"cluster {k}: n_inliers {g['n_inliers'][k]} vs {ref_n}"
+            if "n_near_tau" in g:
+                assert int(g["n_near_tau"][k]) == ref_near
+        if ref_status != oracle.CLUSTER_OK:
+            continue
+        if masks_equal:
+            dv = max(abs(float(g["vx"][k]) - ref_vx), abs(float(g["vy"][k]) - ref_vy))
+            stats["max_dv"] = max(stats["max_dv"], dv)
+            assert dv <= V_TOL, f"cluster {k}: |dv| = {dv}"
+            speed = math.hypot(ref_vx, ref_vy)
+            if speed >= 0.01:
+                dh = abs(math.remainder(float(g["heading"][k]) - ref_hd, 2 * math.pi))
+                stats["max_dheading"] = max(stats["max_dheading"], dh)
+                assert dh <= 2e-4 / speed + 1e-6, f"cluster {k}: heading off by {dh}"
+    return stats
+
+
+def report(name: str, stats: dict) -> None:
+    print(f"[parity] {name}: {stats}", file=sys.stderr, flush=True)

@@ -1,0 +1,118 @@
+"""The C-ABI library (CPU only): it loads, exports every function include/rv.h
+declares, sizes workspaces, and rejects bad arguments on the host before any
+HIP call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rv.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2012_12618_amd import binding
+
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2012_12618_amd import build
+
+        build.build()
+    return binding.load_library()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rv_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    assert {"rv_estimate_velocity", "rv_workspace_bytes", "rv_last_error"} <= set(names)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_header_constants_match_binding():
+    from paper_2012_12618_amd import binding
+
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"(RV_[A-Z_]+)\s*=\s*(-?\d+)", text))
+    for name, value in consts.items():
+        assert getattr(binding, name) == int(value), name
+    assert "RV_MIN_SEED_SEPARATION 1e-3" in text and binding.RV_MIN_SEED_SEPARATION == 1e-3
+    assert "RV_NEAR_TAU_WINDOW 1e-5" in text and binding.RV_NEAR_TAU_WINDOW == 1e-5
+
+
+def test_workspace_bytes(lib):
+    from paper_2012_12618_amd import binding
+
+    a = binding.rv_workspace_bytes(64, 7000, 256)
+    b = binding.rv_workspace_bytes(4096, 2_700_000, 1024)
+    assert 0 < a < b
+    assert binding.rv_workspace_bytes(-1, 10, 8) == 0
+    # 28 bytes per point plus 13 per hypothesis, 256-byte aligned sections
+    assert b >= 28 * 2_700_000 + 13 * 4096 * 1024
+    assert b % 256 == 0
+
+
+def _call(lib, **kw):
+    args = dict(theta=None, vd=None, offsets=None, K=1, N=10, H=16, tau=0.15, seed=1,
+                vx=None, vy=None, heading=None, n_in=None, status=None, near=None, bits=None,
+                hc=None, best=None, ws=None, ws_bytes=0, stream=None)
+    args.update(kw)
+    P = ctypes.c_void_p
+    return lib.rv_estimate_velocity(
+        args["theta"], args["vd"], args["offsets"], args["K"], args["N"], args["H"], args["tau"],
+        args["seed"], args["vx"], args["vy"], args["heading"], args["n_in"], args["status"],
+        args["near"], args["bits"], args["hc"], args["best"], args["ws"], args["ws_bytes"],
+        args["stream"])
+
+
+def test_host_argument_checks(lib):
+    fake = ctypes.c_void_p(4096)  # never dereferenced: the checks fail first
+    ok = dict(theta=fake, vd=fake, offsets=fake, vx=fake, vy=fake, heading=fake, n_in=fake,
+              status=fake)
+    cases = [
+        (dict(ok, H=0), -1, "n_hyp"),
+        (dict(ok, H=(1 << 20) + 1), -1, "n_hyp"),
+        (dict(ok, tau=0.0), -1, "tau"),
+        (dict(ok, tau=float("nan")), -1, "tau"),
+        (dict(ok, tau=float("inf")), -1, "tau"),
+        (dict(ok, K=-1), -1, "n_clusters"),
+        (dict(ok, N=-5), -1, "n_points"),
+        (dict(ok, N=2**31), -1, "n_points"),
+        (dict(ok, offsets=None), -1, "cluster_offsets"),
+        (dict(ok, theta=None), -1, "theta"),
+        (dict(ok, vx=None), -1, "output"),
+        (dict(ok, status=None), -1, "output"),
+        (dict(ok), -2, "workspace"),
+        (dict(ok, ws=fake, ws_bytes=10), -2, "workspace"),
+        (dict(ok, ws=ctypes.c_void_p(4096 + 8), ws_bytes=1 << 30), -2, "aligned"),
+    ]
+    for kw, code, word in cases:
+        assert _call(lib, **kw) == code, kw
+        assert word in lib.rv_last_error().decode()
+    # nothing to do: no clusters -> OK without touching the GPU
+    assert _call(lib, offsets=fake, K=0, N=0, ws=fake, ws_bytes=1 << 20) == 0
+    assert lib.rv_last_error().decode() == ""
+
+
+def test_philox_hook_argument_checks(lib):
+    assert lib.rv_philox4x32_10(None, None, None, -1, None) == -1
+    assert lib.rv_philox4x32_10(None, None, None, 0, None) == 0
+    assert lib.rv_philox4x32_10(None, None, None, 5, None) == -1
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2012_12618_amd import binding
+
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        binding.load_library()

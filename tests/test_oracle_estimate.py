@@ -238,8 +238,9 @@ def test_power_of_two_scaling_is_bitwise(oracle_mod, k2):
     frame, H, tau = synth.make_workload("small")
     base = oracle_mod.estimate_velocity(frame.theta, frame.vd, frame.offsets, H, tau, seed=4, debug=True)
     f = 2.0**k2
+    tau_s = float(np.float32(tau)) * f  # exactly the float32 tau scaled
     sc = oracle_mod.estimate_velocity(frame.theta, (frame.vd * f).astype(np.float32), frame.offsets,
-                                      H, tau * f, seed=4, debug=True)
+                                      H, tau_s, seed=4, debug=True)
     assert np.array_equal(sc.inlier_mask, base.inlier_mask)
     assert np.array_equal(sc.n_inliers, base.n_inliers)
     assert np.array_equal(sc.best_hyp, base.best_hyp)
@@ -387,3 +388,21 @@ def test_comparable_to_sklearn_ransac(oracle_mod):
     ours, theirs = np.median(ours), np.median(theirs)
     assert ours < 0.05 and theirs < 0.05
     assert 0.5 < ours / theirs < 2.0
+
+
+def test_fit_hypothesis_reproduces_the_kept_hypothesis(oracle_mod):
+    frame, H, tau = synth.make_workload("small")
+    r = oracle_mod.estimate_velocity(frame.theta, frame.vd, frame.offsets, H, tau, seed=17, debug=True)
+    for k in (0, 7, 63):
+        f = oracle_mod.fit_hypothesis(frame.theta, frame.vd, frame.offsets, tau, 17, k, r.best_hyp[k])
+        lo, hi = frame.offsets[k], frame.offsets[k + 1]
+        assert f.vx == r.vx[k] and f.vy == r.vy[k] and f.heading == r.heading[k]
+        assert f.n_inliers == r.n_inliers[k] and f.n_near_tau == r.n_near_tau[k]
+        assert np.array_equal(f.mask, r.inlier_mask[lo:hi])
+        # another valid hypothesis: its mask is what its count says
+        h2 = int(np.flatnonzero(r.hyp_valid[k])[-1])
+        g = oracle_mod.fit_hypothesis(frame.theta, frame.vd, frame.offsets, tau, 17, k, h2)
+        assert g.n_inliers == r.hyp_count[k, h2]
+    # a degenerate hypothesis is reported as such
+    th = np.full(6, 0.2, np.float32)
+    assert oracle_mod.fit_hypothesis(th, th, np.array([0, 6], np.int32), 0.15, 1, 0, 0) is None
