@@ -46,6 +46,10 @@ constexpr int kWave = 64;
 constexpr int kHypPerWave = 64;         // one count slot per lane
 constexpr int kHypPerBlock = 256;       // 4 waves x 64 hypotheses
 constexpr int kRowsMax = 16;            // rows of 64 points held in registers per pass
+constexpr int kHypGroup = 8;            // hypotheses per scalar load in the scoring loop
+constexpr int kXcds = 8;                // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr int kSizeClasses = 128;       // quarter-octave size classes for the dispatch order
+constexpr int kPlanBlock = 1024;
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
 constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
@@ -177,35 +181,77 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(
     if (bits != nullptr && p < n_words) bits[p] = 0u;
 }
 
+// Hypotheses are stored in rows of n_hyp_pad = n_hyp rounded up to kHypGroup
+// (the padding holds NaN and never counts), so the scoring loop can fetch a
+// full group of kHypGroup (vx, vy) pairs with one scalar load.
 __global__ __launch_bounds__(kBlock) void hyp_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd,
-    const int32_t *__restrict__ off, int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster,
-    uint32_t key0, uint32_t key1, const double *__restrict__ c64,
+    const int32_t *__restrict__ off, int64_t n_points, int32_t n_hyp, int32_t n_hyp_pad,
+    int32_t blocks_per_cluster, uint32_t key0, uint32_t key1, const double *__restrict__ c64,
     const double *__restrict__ s64, float2 *__restrict__ hyp, uint8_t *__restrict__ valid) {
     const int64_t k = blockIdx.x / blocks_per_cluster;
     const int64_t h = (int64_t)(blockIdx.x % blocks_per_cluster) * kBlock + threadIdx.x;
-    if (h >= n_hyp) return;
+    if (h >= n_hyp_pad) return;
+    const float qnan = __builtin_nanf("");
     const Span sp = cluster_span(off, k, n_points);
-    const int64_t q = k * n_hyp + h;
-    if (!sp.ok || sp.n < 2) {
-        hyp[q] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-        valid[q] = 0;
+    if (h >= n_hyp || !sp.ok || sp.n < 2) {
+        hyp[k * n_hyp_pad + h] = make_float2(qnan, qnan);
+        if (h < n_hyp) valid[k * n_hyp + h] = 0;
         return;
     }
     const Hypothesis hy =
         make_hypothesis(theta, vd, c64, s64, sp, (uint32_t)h, (uint32_t)k, key0, key1);
-    hyp[q] = make_float2((float)hy.vx, (float)hy.vy);
-    valid[q] = hy.valid ? 1 : 0;
+    hyp[k * n_hyp_pad + h] = make_float2((float)hy.vx, (float)hy.vy);
+    valid[k * n_hyp + h] = hy.valid ? 1 : 0;
 }
 
-// R rows of 64 points per lane against nh wave-uniform hypotheses; returns the
-// count of hypothesis q in lane q.
+// Size class of a cluster for the dispatch order: quarter-octave buckets of n,
+// larger n -> larger class; clusters with fewer than two points get class 0.
+__device__ __forceinline__ int size_class(int64_t n) {
+    if (n < 2) return 0;
+    const uint32_t u = n > 0x7FFFFFFF ? 0x7FFFFFFFu : (uint32_t)n;
+    const int e = 31 - __builtin_clz(u);                      // floor(log2 n) >= 1
+    const int frac = e >= 2 ? (int)((u >> (e - 2)) & 3u) : (int)((u << (2 - e)) & 3u);
+    const int c = 1 + 4 * e + frac;
+    return c < kSizeClasses ? c : kSizeClasses - 1;
+}
+
+// Dispatch order of the clusters: a counting sort by decreasing size class, so
+// the longest work items start first (longest-processing-time-first).  The
+// order inside a class depends on atomics; it only affects scheduling.
+__global__ __launch_bounds__(kPlanBlock) void plan_kernel(const int32_t *__restrict__ off,
+                                                          int64_t n_clusters, int64_t n_points,
+                                                          int32_t *__restrict__ order) {
+    __shared__ uint32_t count[kSizeClasses];
+    __shared__ uint32_t start[kSizeClasses];
+    for (int c = threadIdx.x; c < kSizeClasses; c += kPlanBlock) count[c] = 0;
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < n_clusters; k += kPlanBlock)
+        atomicAdd(&count[size_class(cluster_span(off, k, n_points).n)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t at = 0;
+        for (int c = kSizeClasses - 1; c >= 0; --c) {
+            start[c] = at;
+            at += count[c];
+        }
+    }
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < n_clusters; k += kPlanBlock) {
+        const uint32_t pos = atomicAdd(&start[size_class(cluster_span(off, k, n_points).n)], 1u);
+        order[pos] = (int32_t)k;
+    }
+}
+
+// R rows of 64 points per lane (registers) against ng groups of kHypGroup
+// wave-uniform hypotheses (scalar loads, one group fetched ahead); returns the
+// count of hypothesis q of the wave in lane q.
 template <int R>
 __device__ __forceinline__ uint32_t score_rows(const float *__restrict__ c32,
                                                const float *__restrict__ s32,
                                                const float *__restrict__ v32, int64_t base,
                                                int64_t end, int lane,
-                                               const float2 *__restrict__ hp, int nh,
+                                               const float4 *__restrict__ hp, int ng,
                                                float tau) {
     float c[R], s[R], v[R];
 #pragma unroll
@@ -221,26 +267,48 @@ __device__ __forceinline__ uint32_t score_rows(const float *__restrict__ c32,
         }
     }
     uint32_t counts = 0;
-    for (int q = 0; q < nh; ++q) {
-        const float2 hv = hp[q];
-        uint32_t n = 0;
+    float4 h0 = hp[0], h1 = hp[1], h2 = hp[2], h3 = hp[3];
+    for (int g = 0; g < ng; ++g) {
+        const int gn = g + 1 < ng ? g + 1 : g;
+        const float4 n0 = hp[4 * gn], n1 = hp[4 * gn + 1], n2 = hp[4 * gn + 2],
+                     n3 = hp[4 * gn + 3];
+        const float hx[kHypGroup] = {h0.x, h0.z, h1.x, h1.z, h2.x, h2.z, h3.x, h3.z};
+        const float hy[kHypGroup] = {h0.y, h0.w, h1.y, h1.w, h2.y, h2.w, h3.y, h3.w};
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float t = __builtin_fmaf(-hv.x, c[r], v[r]);
-            const float e = __builtin_fmaf(-hv.y, s[r], t);
-            n += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(__builtin_fabsf(e) < tau));
+        for (int u = 0; u < kHypGroup; ++u) {
+            uint32_t n = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float t = __builtin_fmaf(-hx[u], c[r], v[r]);
+                const float e = __builtin_fmaf(-hy[u], s[r], t);
+                n += (uint32_t)__builtin_popcountll(
+                    __builtin_amdgcn_ballot_w64(__builtin_fabsf(e) < tau));
+            }
+            counts = (uint32_t)amdgcn_writelane((int)n, g * kHypGroup + u, (int)counts);
         }
-        counts = (uint32_t)amdgcn_writelane((int)n, q, (int)counts);
+        h0 = n0;
+        h1 = n1;
+        h2 = n2;
+        h3 = n3;
     }
     return counts;
 }
 
+// Work item = (cluster, block of 256 hypotheses); the item of block i is chosen
+// so that clusters are taken in the planned order and all items of one cluster
+// run on the same XCD (blocks are dealt to the 8 XCDs round-robin), sharing
+// that XCD's L2 copy of the cluster's points.
 __global__ __launch_bounds__(kBlock) void score_kernel(
-    const int32_t *__restrict__ off, int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster,
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
+    int64_t n_points, int32_t n_hyp, int32_t n_hyp_pad, int32_t blocks_per_cluster,
     const float *__restrict__ c32, const float *__restrict__ s32, const float *__restrict__ v32,
     const float2 *__restrict__ hyp, float tau, int32_t *__restrict__ counts) {
-    const int64_t k = blockIdx.x / blocks_per_cluster;
-    const int b = blockIdx.x % blocks_per_cluster;
+    const uint32_t xcd = blockIdx.x % kXcds;
+    const uint32_t r = blockIdx.x / kXcds;
+    const int64_t j = xcd + (int64_t)kXcds * (r / (uint32_t)blocks_per_cluster);
+    if (j >= n_clusters) return;
+    const int b = (int)(r % (uint32_t)blocks_per_cluster);
+    const int64_t k = order[j];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const int64_t h0 = (int64_t)b * kHypPerBlock + wave * kHypPerWave;
@@ -251,7 +319,8 @@ __global__ __launch_bounds__(kBlock) void score_kernel(
         if (lane < nh) counts[k * n_hyp + h0 + lane] = 0;
         return;
     }
-    const float2 *hp = hyp + k * n_hyp + h0;
+    const int ng = (nh + kHypGroup - 1) / kHypGroup;
+    const float4 *hp = reinterpret_cast<const float4 *>(hyp + k * n_hyp_pad + h0);
     const int64_t end = sp.lo + sp.n;
     uint32_t total = 0;
     for (int64_t base = sp.lo; base < end; base += (int64_t)kRowsMax * kWave) {
@@ -259,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(
         const int rows = (int)(left < kRowsMax ? left : kRowsMax);
         switch (rows) {
 #define RV_ROWS(R) \
-    case R: total += score_rows<R>(c32, s32, v32, base, end, lane, hp, nh, tau); break;
+    case R: total += score_rows<R>(c32, s32, v32, base, end, lane, hp, ng, tau); break;
             RV_ROWS(1) RV_ROWS(2) RV_ROWS(3) RV_ROWS(4) RV_ROWS(5) RV_ROWS(6) RV_ROWS(7)
             RV_ROWS(8) RV_ROWS(9) RV_ROWS(10) RV_ROWS(11) RV_ROWS(12) RV_ROWS(13)
             RV_ROWS(14) RV_ROWS(15) RV_ROWS(16)
@@ -461,8 +530,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t c32, s32, v32, c64, s64, hyp, valid, counts, total;
+    size_t c32, s32, v32, c64, s64, hyp, valid, counts, order, total;
 };
+
+int64_t padded_hyp(int32_t n_hyp) { return ((int64_t)n_hyp + kHypGroup - 1) / kHypGroup * kHypGroup; }
 
 Layout make_layout(int64_t n_clusters, int64_t n_points, int32_t n_hyp) {
     Layout L;
@@ -474,9 +545,11 @@ Layout make_layout(int64_t n_clusters, int64_t n_points, int32_t n_hyp) {
     L.v32 = at; at = align_up(at + np * sizeof(float));
     L.c64 = at; at = align_up(at + np * sizeof(double));
     L.s64 = at; at = align_up(at + np * sizeof(double));
-    L.hyp = at; at = align_up(at + nq * sizeof(float2));
+    const size_t nq_pad = (size_t)n_clusters * (size_t)padded_hyp(n_hyp);
+    L.hyp = at; at = align_up(at + nq_pad * sizeof(float2));
     L.valid = at; at = align_up(at + nq * sizeof(uint8_t));
     L.counts = at; at = align_up(at + nq * sizeof(int32_t));
+    L.order = at; at = align_up(at + (size_t)n_clusters * sizeof(int32_t));
     L.total = at;
     return L;
 }
@@ -541,8 +614,11 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
         (vx == nullptr || vy == nullptr || heading == nullptr || n_inliers == nullptr ||
          status == nullptr))
         return fail(RV_ERR_INVALID_ARG, "a required output is NULL");
-    const int64_t blocks_per_cluster = ((int64_t)n_hyp + kHypPerBlock - 1) / kHypPerBlock;
-    if (n_clusters > (int64_t)INT32_MAX / blocks_per_cluster)
+    const int64_t n_hyp_pad = padded_hyp(n_hyp);
+    const int64_t score_bpc = ((int64_t)n_hyp + kHypPerBlock - 1) / kHypPerBlock;
+    const int64_t hyp_bpc = (n_hyp_pad + kBlock - 1) / kBlock;
+    const int64_t clusters_xcd = (n_clusters + kXcds - 1) / kXcds * kXcds;
+    if (clusters_xcd > (int64_t)INT32_MAX / hyp_bpc)
         return fail(RV_ERR_INVALID_ARG, "n_clusters * ceil(n_hyp / 256) exceeds 2^31 - 1");
     const Layout L = make_layout(n_clusters, n_points, n_hyp);
     if (workspace == nullptr || workspace_bytes < L.total)
@@ -561,6 +637,7 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     float2 *hyp = (float2 *)(ws + L.hyp);
     uint8_t *valid = (uint8_t *)(ws + L.valid);
     int32_t *counts = hyp_counts != nullptr ? hyp_counts : (int32_t *)(ws + L.counts);
+    int32_t *order = (int32_t *)(ws + L.order);
     const uint32_t key0 = (uint32_t)(seed & 0xFFFFFFFFu), key1 = (uint32_t)(seed >> 32);
     const int64_t n_words = inlier_bits != nullptr ? (n_points + 31) / 32 : 0;
     hipStream_t st = (hipStream_t)stream;
@@ -570,20 +647,20 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     if (timed) (void)hipEventRecord(tc.ev[0], st);
 
     const int64_t prep_items = n_points > n_words ? n_points : n_words;
-    if (prep_items > 0) {
-        const int64_t grid = (prep_items + kBlock - 1) / kBlock;
-        if (grid > INT32_MAX) return fail(RV_ERR_INVALID_ARG, "n_points too large");
-        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)grid), dim3(kBlock), 0, st, theta, vd,
-                           n_points, c32, s32, v32, c64, s64, inlier_bits, n_words);
-    }
+    if (prep_items > 0)
+        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((prep_items + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, theta, vd, n_points, c32, s32, v32, c64, s64,
+                           inlier_bits, n_words);
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, cluster_offsets,
+                       n_clusters, n_points, order);
     if (timed) (void)hipEventRecord(tc.ev[1], st);
-    const unsigned work_blocks = (unsigned)(n_clusters * blocks_per_cluster);
-    hipLaunchKernelGGL(hyp_kernel, dim3(work_blocks), dim3(kBlock), 0, st, theta, vd,
-                       cluster_offsets, n_points, n_hyp, (int32_t)blocks_per_cluster, key0, key1,
-                       c64, s64, hyp, valid);
+    hipLaunchKernelGGL(hyp_kernel, dim3((unsigned)(n_clusters * hyp_bpc)), dim3(kBlock), 0, st,
+                       theta, vd, cluster_offsets, n_points, n_hyp, (int32_t)n_hyp_pad,
+                       (int32_t)hyp_bpc, key0, key1, c64, s64, hyp, valid);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
-    hipLaunchKernelGGL(score_kernel, dim3(work_blocks), dim3(kBlock), 0, st, cluster_offsets,
-                       n_points, n_hyp, (int32_t)blocks_per_cluster, c32, s32, v32,
+    hipLaunchKernelGGL(score_kernel, dim3((unsigned)(clusters_xcd * score_bpc)), dim3(kBlock), 0,
+                       st, cluster_offsets, (const int32_t *)order, n_clusters, n_points, n_hyp,
+                       (int32_t)n_hyp_pad, (int32_t)score_bpc, c32, s32, v32,
                        (const float2 *)hyp, tau, counts);
     if (timed) (void)hipEventRecord(tc.ev[3], st);
     hipLaunchKernelGGL(refit_kernel, dim3((unsigned)n_clusters), dim3(kBlock), 0, st,
