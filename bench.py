@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark of the per-cluster RANSAC velocity/heading estimator on one MI355X.
 
-A step is one full estimate of one synthetic frame (prep, hypotheses, scoring,
-refit) with the frame already resident in HBM.  Default workload: the dense
+A step is one full estimate of one synthetic frame (all three kernels: point
+staging, hypotheses and scoring, refit) with the frame already resident in HBM.  Default workload: the dense
 frame (4096 clusters, log-uniform sizes in [8, 4096] points, 30 % outliers,
 1024 hypotheses per cluster, tau = 0.15 m/s).
 
@@ -116,7 +116,7 @@ def main() -> int:
     evals_per_s = evals / sec
     clusters_per_s = K / sec
     stage_avg = [x / max(n_calls, 1) for x in stage_ms]
-    score_ms = stage_avg[2]
+    score_ms = stage_avg[binding.STAGE_NAMES.index("score")]
     achieved_tflops = FLOP_PER_EVAL * evals / (score_ms / 1e3) / 1e12
 
     # Frame latency: pinned host frame -> device -> estimate -> results in host memory.

@@ -115,10 +115,11 @@ const char *rv_last_error(void);
 
 /*
  * Instrumentation (not part of the estimate).  While enabled, every
- * rv_estimate_velocity call records HIP events around each of its kernels on
- * its stream.  rv_stage_times waits for the recorded events, writes the summed
- * milliseconds per stage (prep, hypotheses, scoring, refit) into ms[0..3],
- * the number of calls into *n_calls, and clears the record.  Returns RV_OK or
+ * rv_estimate_velocity call records HIP events around each of its three
+ * kernels on its stream.  rv_stage_times waits for the recorded events, writes
+ * the summed milliseconds per kernel (ms[0]: point staging and dispatch
+ * planning, ms[1]: hypotheses and scoring, ms[2]: selection and refit) and the
+ * number of calls into *n_calls, and clears the record.  Returns RV_OK or
  * RV_ERR_HIP.
  */
 int rv_stage_timing(int enable);

@@ -29,8 +29,8 @@ RV_MIN_SEED_SEPARATION = 1e-3
 RV_NEAR_TAU_WINDOW = 1e-5
 RV_MAX_HYP = 1 << 20
 
-N_STAGES = 4
-STAGE_NAMES = ("prep", "hyp", "score", "refit")
+N_STAGES = 3
+STAGE_NAMES = ("prep", "score", "refit")
 
 _lib = None
 
@@ -180,7 +180,7 @@ def rv_stage_timing(enable: bool) -> None:
 
 
 def rv_stage_times() -> tuple[list[float], int]:
-    """(summed ms per stage [prep, hyp, score, refit], number of timed calls)."""
+    """(summed ms per kernel [prep, score, refit], number of timed calls)."""
     ms = (ctypes.c_double * N_STAGES)()
     n = ctypes.c_int64()
     _check(load_library().rv_stage_times(ms, ctypes.byref(n)))

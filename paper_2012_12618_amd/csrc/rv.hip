@@ -1,23 +1,25 @@
 // rv.hip -- gfx950 kernels and host entry points of the per-cluster RANSAC
 // velocity and heading estimator declared in include/rv.h.
 //
-// One call enqueues four kernels on the caller's stream:
+// One call enqueues three kernels on the caller's stream:
 //   prep    one thread per point: FP64 sincos of the azimuth; stages float32
-//           (cos, sin, v_d) for scoring and FP64 (cos, sin) for the solves;
-//           clears the optional frame-wide inlier bitmask.
-//   hyp     one thread per (cluster, hypothesis): Philox4x32-10 seed pair,
-//           validity, FP64 2x2 solve (Sec. 3.2, Eq. 6 for two seeds), stored
-//           rounded to float32 (Sec. 3.1, Alg. 1: slope/intercept step).
-//   score   the hot loop (Sec. 3.1, Alg. 1: the per-point distance test).
-//           Workgroup = (cluster, block of 256 hypotheses); each wave owns 64
-//           hypotheses.  Lanes hold points in registers (rows of 64 points);
-//           the hypothesis (vx, vy) is wave-uniform and read through scalar
-//           loads.  Per point: two float32 FMAs and one compare whose 64-lane
-//           ballot is popcounted by the scalar unit.  Counts go to global memory.
-//   refit   one workgroup per cluster: arg-max over the counts (lowest index
-//           on ties), FP64 re-classification under the kept hypothesis, FP64
-//           normal-equation sums in a fixed reduction tree, 2x2 solve (Sec. 3.2,
-//           Eq. 7, Alg. 2) and atan2 heading (Eq. 8).
+//           (cos, sin) and v_d for scoring and FP64 (cos, sin) for the solves; clears the optional frame-wide inlier bitmask and the
+//           per-cluster best keys.  Its last workgroup plans the dispatch
+//           order: clusters by decreasing size.
+//   score   the hot loop.  Workgroup = (cluster, block of 256 hypotheses).
+//           Each thread draws one Philox4x32-10 seed pair and solves the 2x2
+//           system in FP64 (Sec. 3.1, Alg. 1: seeds, slope and intercept, as the
+//           velocity profile of Sec. 3.2, Eq. 6); the float32 (vx, vy) go to LDS.
+//           Each wave then owns 64 hypotheses: lanes hold the cluster's points in
+//           registers (rows of 64 points), every lane reads the same hypothesis
+//           from LDS, and per point two float32 FMAs and one compare produce a
+//           64-lane ballot that the scalar unit popcounts (Alg. 1's distance test
+//           and inlier count).  The best (count, lowest index) key of the block
+//           is merged per cluster with a 64-bit atomic maximum (Sec. 3.1: the
+//           trial with the most inliers is kept).
+//   refit   one workgroup per cluster: FP64 re-classification under the kept
+//           hypothesis, FP64 normal-equation sums in a fixed reduction tree,
+//           2x2 solve (Sec. 3.2, Eq. 7, Alg. 2) and atan2 heading (Eq. 8).
 //
 // No floating-point atomics and fixed reduction orders: results are bitwise
 // reproducible run to run and independent of the other clusters in the frame.
@@ -41,15 +43,15 @@ __device__ int amdgcn_writelane(int value, int lane, int old) __asm("llvm.amdgcn
 
 namespace {
 
-constexpr int kBlock = 256;             // threads per workgroup (4 x wave64)
 constexpr int kWave = 64;
-constexpr int kHypPerWave = 64;         // one count slot per lane
-constexpr int kHypPerBlock = 256;       // 4 waves x 64 hypotheses
-constexpr int kRowsMax = 16;            // rows of 64 points held in registers per pass
-constexpr int kHypGroup = 8;            // hypotheses per scalar load in the scoring loop
+constexpr int kScoreBlock = 256;        // score: 4 waves x 64 hypotheses, one per thread
+constexpr int kRefitBlock = 256;
 constexpr int kXcds = 8;                // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr int kPrepBlock = 256;
+constexpr int kRowsMax = 16;            // rows of 64 points held in registers per pass
+constexpr int kHypGroup = 4;            // hypotheses per LDS fetch in the scoring loop
 constexpr int kSizeClasses = 128;       // quarter-octave size classes for the dispatch order
-constexpr int kPlanBlock = 1024;
+constexpr int64_t kPlanMaxClusters = 1 << 16;  // above this, clusters run in index order
 constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
 constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
@@ -103,6 +105,16 @@ __device__ __forceinline__ Span cluster_span(const int32_t *__restrict__ off, in
     return s;
 }
 
+// Staged points: float32 (cos, sin) and v_d for scoring (v_d = +inf marks a
+// point whose azimuth or Doppler value is not finite), FP64 (cos, sin) for the
+// solves and the refit, and the caller's azimuths for the seed-separation test.
+struct Points {
+    const float2 *cs32;
+    const float *v32;
+    const double2 *cs64;
+    const float *theta;
+};
+
 struct Hypothesis {
     double vx, vy;
     bool valid;
@@ -110,27 +122,26 @@ struct Hypothesis {
 
 // Hypothesis h of cluster k: seed pair, validity and the FP64 2x2 solve of
 // v_d = vx cos + vy sin at the two seeds (Cramer's rule).
-__device__ __forceinline__ Hypothesis make_hypothesis(
-    const float *__restrict__ theta, const float *__restrict__ vd,
-    const double *__restrict__ c64, const double *__restrict__ s64, Span sp, uint32_t h,
-    uint32_t k, uint32_t key0, uint32_t key1) {
+__device__ __forceinline__ Hypothesis make_hypothesis(const Points &pts, Span sp, uint32_t h,
+                                                      uint32_t k, uint32_t key0, uint32_t key1) {
     const uint4 u = philox4x32_10(make_uint4(h, k, 0u, 0u), key0, key1);
     uint32_t i, j;
     seed_pair(u.x, u.y, (uint32_t)sp.n, i, j);
     const int64_t pi = sp.lo + i, pj = sp.lo + j;
-    const float ti = theta[pi], tj = theta[pj], vi = vd[pi], vj = vd[pj];
+    const float vi = pts.v32[pi], vj = pts.v32[pj];
     Hypothesis hy;
-    hy.valid = isfinite(ti) && isfinite(tj) && isfinite(vi) && isfinite(vj) &&
-               fabs((double)tj - (double)ti) >= RV_MIN_SEED_SEPARATION;
+    hy.valid = isfinite(vi) && isfinite(vj) &&
+               fabs((double)pts.theta[pj] - (double)pts.theta[pi]) >= RV_MIN_SEED_SEPARATION;
     if (!hy.valid) {
         hy.vx = hy.vy = __builtin_nan("");
         return hy;
     }
-    const double ci = c64[pi], si = s64[pi], cj = c64[pj], sj = s64[pj];
+    const double2 ai = pts.cs64[pi], bj = pts.cs64[pj];
+    const double ci = ai.x, si = ai.y, cj = bj.x, sj = bj.y;
     const double dvi = vi, dvj = vj;
-    const double det = ci * sj - si * cj;
-    hy.vx = (dvi * sj - dvj * si) / det;
-    hy.vy = (ci * dvj - cj * dvi) / det;
+    const double inv_det = 1.0 / (ci * sj - si * cj);
+    hy.vx = (dvi * sj - dvj * si) * inv_det;
+    hy.vy = (ci * dvj - cj * dvi) * inv_det;
     return hy;
 }
 
@@ -159,52 +170,6 @@ __device__ __forceinline__ int wave_sum_i(int v) {
 // Kernels
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void prep_kernel(
-    const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
-    float *__restrict__ c32, float *__restrict__ s32, float *__restrict__ v32,
-    double *__restrict__ c64, double *__restrict__ s64, uint32_t *__restrict__ bits,
-    int64_t n_words) {
-    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p < n_points) {
-        const float t = theta[p], v = vd[p];
-        double s, c;
-        sincos((double)t, &s, &c);
-        const bool ok = isfinite(t) && isfinite(v);
-        c64[p] = c;
-        s64[p] = s;
-        // A non-finite point scores as (0, 0, +inf): its residual is inf or NaN,
-        // never below tau.
-        c32[p] = ok ? (float)c : 0.0f;
-        s32[p] = ok ? (float)s : 0.0f;
-        v32[p] = ok ? v : __builtin_inff();
-    }
-    if (bits != nullptr && p < n_words) bits[p] = 0u;
-}
-
-// Hypotheses are stored in rows of n_hyp_pad = n_hyp rounded up to kHypGroup
-// (the padding holds NaN and never counts), so the scoring loop can fetch a
-// full group of kHypGroup (vx, vy) pairs with one scalar load.
-__global__ __launch_bounds__(kBlock) void hyp_kernel(
-    const float *__restrict__ theta, const float *__restrict__ vd,
-    const int32_t *__restrict__ off, int64_t n_points, int32_t n_hyp, int32_t n_hyp_pad,
-    int32_t blocks_per_cluster, uint32_t key0, uint32_t key1, const double *__restrict__ c64,
-    const double *__restrict__ s64, float2 *__restrict__ hyp, uint8_t *__restrict__ valid) {
-    const int64_t k = blockIdx.x / blocks_per_cluster;
-    const int64_t h = (int64_t)(blockIdx.x % blocks_per_cluster) * kBlock + threadIdx.x;
-    if (h >= n_hyp_pad) return;
-    const float qnan = __builtin_nanf("");
-    const Span sp = cluster_span(off, k, n_points);
-    if (h >= n_hyp || !sp.ok || sp.n < 2) {
-        hyp[k * n_hyp_pad + h] = make_float2(qnan, qnan);
-        if (h < n_hyp) valid[k * n_hyp + h] = 0;
-        return;
-    }
-    const Hypothesis hy =
-        make_hypothesis(theta, vd, c64, s64, sp, (uint32_t)h, (uint32_t)k, key0, key1);
-    hyp[k * n_hyp_pad + h] = make_float2((float)hy.vx, (float)hy.vy);
-    valid[k * n_hyp + h] = hy.valid ? 1 : 0;
-}
-
 // Size class of a cluster for the dispatch order: quarter-octave buckets of n,
 // larger n -> larger class; clusters with fewer than two points get class 0.
 __device__ __forceinline__ int size_class(int64_t n) {
@@ -217,16 +182,15 @@ __device__ __forceinline__ int size_class(int64_t n) {
 }
 
 // Dispatch order of the clusters: a counting sort by decreasing size class, so
-// the longest work items start first (longest-processing-time-first).  The
+// the longest workgroups start first (longest-processing-time-first).  The
 // order inside a class depends on atomics; it only affects scheduling.
-__global__ __launch_bounds__(kPlanBlock) void plan_kernel(const int32_t *__restrict__ off,
-                                                          int64_t n_clusters, int64_t n_points,
-                                                          int32_t *__restrict__ order) {
+__device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
+                           int64_t n_points, int32_t *__restrict__ order) {
     __shared__ uint32_t count[kSizeClasses];
     __shared__ uint32_t start[kSizeClasses];
-    for (int c = threadIdx.x; c < kSizeClasses; c += kPlanBlock) count[c] = 0;
+    for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) count[c] = 0;
     __syncthreads();
-    for (int64_t k = threadIdx.x; k < n_clusters; k += kPlanBlock)
+    for (int64_t k = threadIdx.x; k < n_clusters; k += kPrepBlock)
         atomicAdd(&count[size_class(cluster_span(off, k, n_points).n)], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -237,43 +201,69 @@ __global__ __launch_bounds__(kPlanBlock) void plan_kernel(const int32_t *__restr
         }
     }
     __syncthreads();
-    for (int64_t k = threadIdx.x; k < n_clusters; k += kPlanBlock) {
+    for (int64_t k = threadIdx.x; k < n_clusters; k += kPrepBlock) {
         const uint32_t pos = atomicAdd(&start[size_class(cluster_span(off, k, n_points).n)], 1u);
         order[pos] = (int32_t)k;
     }
 }
 
+// Blocks [0, gridDim.x - 1) stage the points and clear the per-cluster best
+// keys; the last block plans the order (when `order` is non-null).
+__global__ __launch_bounds__(kPrepBlock) void prep_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
+    float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
+    uint32_t *__restrict__ bits,
+    int64_t n_words, const int32_t *__restrict__ off, int64_t n_clusters,
+    int32_t *__restrict__ order, unsigned long long *__restrict__ best_key) {
+    if (blockIdx.x == gridDim.x - 1) {
+        if (order != nullptr) plan_order(off, n_clusters, n_points, order);
+        return;
+    }
+    const int64_t p = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
+    if (p < n_clusters) best_key[p] = 0;
+    if (p < n_points) {
+        const float t = theta[p], v = vd[p];
+        double s, c;
+        sincos((double)t, &s, &c);
+        const bool ok = isfinite(t) && isfinite(v);
+        // A non-finite point is staged as (0, 0, +inf): its float32 residual is
+        // inf or NaN, never below tau, and +inf marks it for the solves and the
+        // refit.
+        cs32[p] = make_float2(ok ? (float)c : 0.0f, ok ? (float)s : 0.0f);
+        v32[p] = ok ? v : __builtin_inff();
+        cs64[p] = make_double2(c, s);
+    }
+    if (bits != nullptr && p < n_words) bits[p] = 0u;
+}
+
 // R rows of 64 points per lane (registers) against ng groups of kHypGroup
-// wave-uniform hypotheses (scalar loads, one group fetched ahead); returns the
-// count of hypothesis q of the wave in lane q.
+// hypotheses read from LDS (broadcast reads: every lane gets the same (vx, vy));
+// returns the count of hypothesis q of the wave in lane q.
 template <int R>
-__device__ __forceinline__ uint32_t score_rows(const float *__restrict__ c32,
-                                               const float *__restrict__ s32,
-                                               const float *__restrict__ v32, int64_t base,
-                                               int64_t end, int lane,
-                                               const float4 *__restrict__ hp, int ng,
-                                               float tau) {
+__device__ __forceinline__ uint32_t score_rows(const float2 *__restrict__ cs_chunk,
+                                               const float *__restrict__ v_chunk, int npts,
+                                               int lane, const float4 *hp, int ng, float tau) {
     float c[R], s[R], v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t p = base + r * kWave + lane;
+        // Uniform row base and row length, one lane offset: no per-row address
+        // registers.
+        const int len = npts - r * kWave;
         c[r] = 0.0f;
         s[r] = 0.0f;
         v[r] = __builtin_inff();
-        if (p < end) {
-            c[r] = c32[p];
-            s[r] = s32[p];
-            v[r] = v32[p];
+        if (lane < len) {
+            const float2 q = cs_chunk[r * kWave + lane];
+            c[r] = q.x;
+            s[r] = q.y;
+            v[r] = v_chunk[r * kWave + lane];
         }
     }
     uint32_t counts = 0;
-    float4 h0 = hp[0], h1 = hp[1], h2 = hp[2], h3 = hp[3];
     for (int g = 0; g < ng; ++g) {
-        const int gn = g + 1 < ng ? g + 1 : g;
-        const float4 n0 = hp[4 * gn], n1 = hp[4 * gn + 1], n2 = hp[4 * gn + 2],
-                     n3 = hp[4 * gn + 3];
-        const float hx[kHypGroup] = {h0.x, h0.z, h1.x, h1.z, h2.x, h2.z, h3.x, h3.z};
-        const float hy[kHypGroup] = {h0.y, h0.w, h1.y, h1.w, h2.y, h2.w, h3.y, h3.w};
+        const float4 h0 = hp[2 * g], h1 = hp[2 * g + 1];
+        const float hx[kHypGroup] = {h0.x, h0.z, h1.x, h1.z};
+        const float hy[kHypGroup] = {h0.y, h0.w, h1.y, h1.w};
 #pragma unroll
         for (int u = 0; u < kHypGroup; ++u) {
             uint32_t n = 0;
@@ -285,50 +275,31 @@ __device__ __forceinline__ uint32_t score_rows(const float *__restrict__ c32,
                     __builtin_amdgcn_ballot_w64(__builtin_fabsf(e) < tau));
             }
             counts = (uint32_t)amdgcn_writelane((int)n, g * kHypGroup + u, (int)counts);
+            // One hypothesis at a time: interleaving several keeps R ballot masks
+            // per hypothesis live and spills scalar registers.
+            __builtin_amdgcn_sched_barrier(0);
         }
-        h0 = n0;
-        h1 = n1;
-        h2 = n2;
-        h3 = n3;
     }
     return counts;
 }
 
-// Work item = (cluster, block of 256 hypotheses); the item of block i is chosen
-// so that clusters are taken in the planned order and all items of one cluster
-// run on the same XCD (blocks are dealt to the 8 XCDs round-robin), sharing
-// that XCD's L2 copy of the cluster's points.
-__global__ __launch_bounds__(kBlock) void score_kernel(
-    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
-    int64_t n_points, int32_t n_hyp, int32_t n_hyp_pad, int32_t blocks_per_cluster,
-    const float *__restrict__ c32, const float *__restrict__ s32, const float *__restrict__ v32,
-    const float2 *__restrict__ hyp, float tau, int32_t *__restrict__ counts) {
-    const uint32_t xcd = blockIdx.x % kXcds;
-    const uint32_t r = blockIdx.x / kXcds;
-    const int64_t j = xcd + (int64_t)kXcds * (r / (uint32_t)blocks_per_cluster);
-    if (j >= n_clusters) return;
-    const int b = (int)(r % (uint32_t)blocks_per_cluster);
-    const int64_t k = order[j];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lane = threadIdx.x % kWave;
-    const int64_t h0 = (int64_t)b * kHypPerBlock + wave * kHypPerWave;
-    if (h0 >= n_hyp) return;
-    const int nh = (int64_t)n_hyp - h0 < kHypPerWave ? (int)((int64_t)n_hyp - h0) : kHypPerWave;
-    const Span sp = cluster_span(off, k, n_points);
-    if (!sp.ok || sp.n < 2) {
-        if (lane < nh) counts[k * n_hyp + h0 + lane] = 0;
-        return;
-    }
+// Inlier counts of the wave's nh hypotheses (LDS at hp) over all points of the
+// cluster; lane q returns the count of hypothesis q.
+__device__ __forceinline__ uint32_t score_cluster(const Points &pts, Span sp,
+                                                  int lane, const float4 *hp, int nh,
+                                                  float tau) {
     const int ng = (nh + kHypGroup - 1) / kHypGroup;
-    const float4 *hp = reinterpret_cast<const float4 *>(hyp + k * n_hyp_pad + h0);
     const int64_t end = sp.lo + sp.n;
     uint32_t total = 0;
     for (int64_t base = sp.lo; base < end; base += (int64_t)kRowsMax * kWave) {
-        const int64_t left = (end - base + kWave - 1) / kWave;
-        const int rows = (int)(left < kRowsMax ? left : kRowsMax);
+        const int64_t left = end - base;
+        const int npts = (int)(left < (int64_t)kRowsMax * kWave ? left : (int64_t)kRowsMax * kWave);
+        const int rows = (npts + kWave - 1) / kWave;
+        const float2 *cs_chunk = pts.cs32 + base;
+        const float *v_chunk = pts.v32 + base;
         switch (rows) {
 #define RV_ROWS(R) \
-    case R: total += score_rows<R>(c32, s32, v32, base, end, lane, hp, ng, tau); break;
+    case R: total += score_rows<R>(cs_chunk, v_chunk, npts, lane, hp, ng, tau); break;
             RV_ROWS(1) RV_ROWS(2) RV_ROWS(3) RV_ROWS(4) RV_ROWS(5) RV_ROWS(6) RV_ROWS(7)
             RV_ROWS(8) RV_ROWS(9) RV_ROWS(10) RV_ROWS(11) RV_ROWS(12) RV_ROWS(13)
             RV_ROWS(14) RV_ROWS(15) RV_ROWS(16)
@@ -336,94 +307,140 @@ __global__ __launch_bounds__(kBlock) void score_kernel(
             default: break;
         }
     }
-    if (lane < nh) counts[k * n_hyp + h0 + lane] = (int32_t)total;
+    return total;
 }
 
-__global__ __launch_bounds__(kBlock) void refit_kernel(
-    const int32_t *__restrict__ off, int64_t n_points, int32_t n_hyp, uint32_t key0,
-    uint32_t key1, const float *__restrict__ theta, const float *__restrict__ vd,
-    const double *__restrict__ c64, const double *__restrict__ s64,
-    const int32_t *__restrict__ counts, const uint8_t *__restrict__ valid, double tau,
-    float *__restrict__ out_vx, float *__restrict__ out_vy, float *__restrict__ out_heading,
-    int32_t *__restrict__ out_n_inliers, uint8_t *__restrict__ out_status,
-    int32_t *__restrict__ out_n_near, uint32_t *__restrict__ bits,
-    int32_t *__restrict__ out_best) {
-    __shared__ uint64_t red_key[kBlock / kWave];
-    __shared__ double red_sum[kBlock / kWave][5];
-    __shared__ int red_cnt[kBlock / kWave][2];
+struct Outputs {
+    float *vx, *vy, *heading;
+    int32_t *n_inliers;
+    uint8_t *status;
+    int32_t *n_near, *best, *hyp_counts;
+    uint32_t *bits;
+};
 
-    const int64_t k = blockIdx.x;
+__device__ __forceinline__ void write_failed(const Outputs &o, int64_t k, uint8_t st) {
+    const float qnan = __builtin_nanf("");
+    o.vx[k] = qnan;
+    o.vy[k] = qnan;
+    o.heading[k] = qnan;
+    o.n_inliers[k] = 0;
+    o.status[k] = st;
+    if (o.n_near) o.n_near[k] = 0;
+    if (o.best) o.best[k] = -1;
+}
+
+// Work item = (cluster, block of 256 hypotheses).  Block i takes the item that
+// keeps clusters in the planned order while all items of one cluster run on the
+// same XCD (blocks are dealt to the 8 XCDs round-robin), sharing that XCD's L2
+// copy of the cluster's points.  Each thread first draws and solves one
+// hypothesis into LDS; each wave then scores 64 of them against every point of
+// the cluster.  The block's best (count, lowest index) key over its valid
+// hypotheses is merged into best_key[k] with a 64-bit atomic maximum, whose
+// result does not depend on the order of the blocks.
+// Eight waves per SIMD: the scoring loop fits in 64 VGPRs.
+__global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))) void score_kernel(
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
+    int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster, uint32_t key0, uint32_t key1,
+    Points pts, float tau, unsigned long long *__restrict__ best_key,
+    int32_t *__restrict__ hyp_counts) {
+    __shared__ float4 s_hyp[kScoreBlock / 2];  // (vx, vy) pairs, two per float4
+    __shared__ unsigned long long s_key[kScoreBlock / kWave];
+    const uint32_t xcd = blockIdx.x % kXcds;
+    const uint32_t r = blockIdx.x / kXcds;
+    const int64_t j = xcd + (int64_t)kXcds * (r / (uint32_t)blocks_per_cluster);
+    if (j >= n_clusters) return;
+    const int b = (int)(r % (uint32_t)blocks_per_cluster);
+    const int64_t k = order != nullptr ? order[j] : j;
+    const int tid = threadIdx.x;
+    const int64_t h = (int64_t)b * kScoreBlock + tid;
+    const Span sp = cluster_span(off, k, n_points);
+    if (!sp.ok || sp.n < 2) {
+        if (hyp_counts != nullptr && h < n_hyp) hyp_counts[k * n_hyp + h] = 0;
+        return;
+    }
+
+    {
+        float hx = __builtin_nanf(""), hy = __builtin_nanf("");
+        if (h < n_hyp) {
+            const Hypothesis hyp = make_hypothesis(pts, sp, (uint32_t)h, (uint32_t)k, key0, key1);
+            hx = (float)hyp.vx;  // NaN exactly when the pair is degenerate
+            hy = (float)hyp.vy;
+        }
+        reinterpret_cast<float2 *>(s_hyp)[tid] = make_float2(hx, hy);
+    }
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = tid % kWave;
+    const int64_t h0 = (int64_t)b * kScoreBlock + wave * kWave;
+    unsigned long long key = 0;
+    if (h0 < n_hyp) {
+        const int nh = (int64_t)n_hyp - h0 < kWave ? (int)((int64_t)n_hyp - h0) : kWave;
+        const uint32_t cnt = score_cluster(pts, sp, lane, s_hyp + wave * (kWave / 2), nh, tau);
+        // The lane's own hypothesis is re-read from LDS rather than kept in
+        // registers through the scoring loop.
+        const int64_t hl = h0 + lane;
+        if (lane < nh) {
+            if (hyp_counts != nullptr) hyp_counts[k * n_hyp + hl] = (int32_t)cnt;
+            if (!__builtin_isnan(reinterpret_cast<const float2 *>(s_hyp)[tid].x))
+                key = ((unsigned long long)cnt << 32) | (0xFFFFFFFFull - (uint32_t)hl);
+        }
+    }
+    key = wave_max_u64(key);
+    if (lane == 0) s_key[wave] = key;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kScoreBlock / kWave; ++w) key = s_key[w] > key ? s_key[w] : key;
+        if (key != 0) atomicMax(&best_key[k], key);
+    }
+}
+
+// One workgroup per cluster, clusters in the planned order: the kept
+// hypothesis (from best_key), FP64 re-classification of every point under it,
+// least-squares refit on its inliers (Sec. 3.2, Eq. 7, Alg. 2: normal equations
+// A^T A v = A^T v_d, summed per thread and reduced in a fixed tree) and heading
+// atan2(vy, vx) (Eq. 8).
+__global__ __launch_bounds__(kRefitBlock) void refit_kernel(
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_points,
+    uint32_t key0, uint32_t key1, Points pts, const unsigned long long *__restrict__ best_key,
+    float tau, Outputs o) {
+    __shared__ double s_sum[kRefitBlock / kWave][5];
+    __shared__ int s_cnt[kRefitBlock / kWave][2];
+    const int64_t k = order != nullptr ? order[blockIdx.x] : (int64_t)blockIdx.x;
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = tid % kWave;
     const Span sp = cluster_span(off, k, n_points);
-    const float qnan = __builtin_nanf("");
-
-    uint8_t st = RV_CLUSTER_OK;
-    if (!sp.ok)
-        st = RV_CLUSTER_BAD_OFFSETS;
-    else if (sp.n < 2)
-        st = RV_CLUSTER_TOO_FEW_POINTS;
-    if (st != RV_CLUSTER_OK) {
-        if (tid == 0) {
-            out_vx[k] = qnan;
-            out_vy[k] = qnan;
-            out_heading[k] = qnan;
-            out_n_inliers[k] = 0;
-            out_status[k] = st;
-            if (out_n_near) out_n_near[k] = 0;
-            if (out_best) out_best[k] = -1;
-        }
+    if (!sp.ok || sp.n < 2) {
+        if (tid == 0) write_failed(o, k, sp.ok ? RV_CLUSTER_TOO_FEW_POINTS : RV_CLUSTER_BAD_OFFSETS);
         return;
     }
-
-    // Keep the valid hypothesis with the most inliers; lowest index on ties.
-    uint64_t key = 0;
-    for (int64_t h = tid; h < n_hyp; h += kBlock) {
-        const int64_t q = k * n_hyp + h;
-        if (valid[q]) {
-            const uint64_t kk = ((uint64_t)(uint32_t)counts[q] << 32) |
-                                (uint64_t)(0xFFFFFFFFu - (uint32_t)h);
-            key = kk > key ? kk : key;
-        }
-    }
-    key = wave_max_u64(key);
-    if (lane == 0) red_key[wave] = key;
-    __syncthreads();
-    key = red_key[0];
-    for (int w = 1; w < kBlock / kWave; ++w) key = red_key[w] > key ? red_key[w] : key;
-    if (key == 0) {
-        if (tid == 0) {
-            out_vx[k] = qnan;
-            out_vy[k] = qnan;
-            out_heading[k] = qnan;
-            out_n_inliers[k] = 0;
-            out_status[k] = RV_CLUSTER_ALL_DEGENERATE;
-            if (out_n_near) out_n_near[k] = 0;
-            if (out_best) out_best[k] = -1;
-        }
+    const unsigned long long best = best_key[k];
+    if (best == 0) {
+        if (tid == 0) write_failed(o, k, RV_CLUSTER_ALL_DEGENERATE);
         return;
     }
-    const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu);
-    const Hypothesis hy =
-        make_hypothesis(theta, vd, c64, s64, sp, hbest, (uint32_t)k, key0, key1);
+    const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+    const Hypothesis hy = make_hypothesis(pts, sp, hbest, (uint32_t)k, key0, key1);
+    const double dtau = tau;
 
-    // Re-classify under the kept hypothesis in FP64 and accumulate the normal
-    // equations (A^T A) v = A^T v_d over its inliers.  Waves walk 64-aligned
-    // global blocks so one ballot maps onto two words of the bitmask.
+    // Threads walk 64-aligned global blocks so one wave ballot maps onto two
+    // words of the frame-wide bitmask.
     const int64_t end = sp.lo + sp.n;
     double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
     int n_in = 0, n_near = 0;
-    for (int64_t p0 = (sp.lo & ~(int64_t)(kWave - 1)) + wave * kWave; p0 < end; p0 += kBlock) {
+    for (int64_t p0 = (sp.lo & ~(int64_t)(kWave - 1)) + (int64_t)wave * kWave; p0 < end;
+         p0 += kRefitBlock) {
         const int64_t p = p0 + lane;
         bool inlier = false;
         if (p >= sp.lo && p < end) {
-            const float t = theta[p], v = vd[p];
-            if (isfinite(t) && isfinite(v)) {
-                const double c = c64[p], s = s64[p], dv = v;
+            const float v = pts.v32[p];  // +inf marks a non-finite point
+            if (isfinite(v)) {
+                const double2 cs = pts.cs64[p];
+                const double c = cs.x, s = cs.y, dv = v;
                 const double res = fabs(dv - hy.vx * c - hy.vy * s);
-                n_near += fabs(res - tau) <= RV_NEAR_TAU_WINDOW ? 1 : 0;
-                if (res < tau) {
+                n_near += fabs(res - dtau) <= RV_NEAR_TAU_WINDOW ? 1 : 0;
+                if (res < dtau) {
                     inlier = true;
                     n_in += 1;
                     scc += c * c;
@@ -434,12 +451,12 @@ __global__ __launch_bounds__(kBlock) void refit_kernel(
                 }
             }
         }
-        if (bits != nullptr) {
+        if (o.bits != nullptr) {
             const uint64_t m = __builtin_amdgcn_ballot_w64(inlier);
             if (lane == 0) {
                 const uint32_t w0 = (uint32_t)m, w1 = (uint32_t)(m >> 32);
-                if (w0) atomicOr(&bits[p0 >> 5], w0);
-                if (w1) atomicOr(&bits[(p0 >> 5) + 1], w1);
+                if (w0) atomicOr(&o.bits[p0 >> 5], w0);
+                if (w1) atomicOr(&o.bits[(p0 >> 5) + 1], w1);
             }
         }
     }
@@ -451,56 +468,57 @@ __global__ __launch_bounds__(kBlock) void refit_kernel(
     n_in = wave_sum_i(n_in);
     n_near = wave_sum_i(n_near);
     if (lane == 0) {
-        red_sum[wave][0] = scc;
-        red_sum[wave][1] = scs;
-        red_sum[wave][2] = sss;
-        red_sum[wave][3] = scv;
-        red_sum[wave][4] = ssv;
-        red_cnt[wave][0] = n_in;
-        red_cnt[wave][1] = n_near;
+        s_sum[wave][0] = scc;
+        s_sum[wave][1] = scs;
+        s_sum[wave][2] = sss;
+        s_sum[wave][3] = scv;
+        s_sum[wave][4] = ssv;
+        s_cnt[wave][0] = n_in;
+        s_cnt[wave][1] = n_near;
     }
     __syncthreads();
     if (tid != 0) return;
-    scc = red_sum[0][0];
-    scs = red_sum[0][1];
-    sss = red_sum[0][2];
-    scv = red_sum[0][3];
-    ssv = red_sum[0][4];
-    n_in = red_cnt[0][0];
-    n_near = red_cnt[0][1];
-    for (int w = 1; w < kBlock / kWave; ++w) {
-        scc += red_sum[w][0];
-        scs += red_sum[w][1];
-        sss += red_sum[w][2];
-        scv += red_sum[w][3];
-        ssv += red_sum[w][4];
-        n_in += red_cnt[w][0];
-        n_near += red_cnt[w][1];
+    scc = s_sum[0][0];
+    scs = s_sum[0][1];
+    sss = s_sum[0][2];
+    scv = s_sum[0][3];
+    ssv = s_sum[0][4];
+    n_in = s_cnt[0][0];
+    n_near = s_cnt[0][1];
+    for (int w = 1; w < kRefitBlock / kWave; ++w) {
+        scc += s_sum[w][0];
+        scs += s_sum[w][1];
+        sss += s_sum[w][2];
+        scv += s_sum[w][3];
+        ssv += s_sum[w][4];
+        n_in += s_cnt[w][0];
+        n_near += s_cnt[w][1];
     }
-    out_n_inliers[k] = n_in;
-    if (out_n_near) out_n_near[k] = n_near;
-    if (out_best) out_best[k] = (int32_t)hbest;
+    o.n_inliers[k] = n_in;
+    if (o.n_near) o.n_near[k] = n_near;
+    if (o.best) o.best[k] = (int32_t)hbest;
     const double det = scc * sss - scs * scs;
     if (n_in < 2 || !(det > 0.0)) {
-        out_vx[k] = qnan;
-        out_vy[k] = qnan;
-        out_heading[k] = qnan;
-        out_status[k] = RV_CLUSTER_SINGULAR_REFIT;
+        const float qnan = __builtin_nanf("");
+        o.vx[k] = qnan;
+        o.vy[k] = qnan;
+        o.heading[k] = qnan;
+        o.status[k] = RV_CLUSTER_SINGULAR_REFIT;
         return;
     }
     const double fvx = (sss * scv - scs * ssv) / det;
     const double fvy = (scc * ssv - scs * scv) / det;
-    out_vx[k] = (float)fvx;
-    out_vy[k] = (float)fvy;
-    out_heading[k] = (float)atan2(fvy, fvx);
-    out_status[k] = RV_CLUSTER_OK;
+    o.vx[k] = (float)fvx;
+    o.vy[k] = (float)fvy;
+    o.heading[k] = (float)atan2(fvy, fvx);
+    o.status[k] = RV_CLUSTER_OK;
 }
 
-__global__ __launch_bounds__(kBlock) void philox_kernel(const uint32_t *__restrict__ ctr,
+__global__ __launch_bounds__(kPrepBlock) void philox_kernel(const uint32_t *__restrict__ ctr,
                                                         const uint32_t *__restrict__ key,
                                                         uint32_t *__restrict__ out,
                                                         int64_t n) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
     if (t >= n) return;
     const uint4 r = philox4x32_10(
         make_uint4(ctr[4 * t], ctr[4 * t + 1], ctr[4 * t + 2], ctr[4 * t + 3]), key[2 * t],
@@ -530,32 +548,24 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t c32, s32, v32, c64, s64, hyp, valid, counts, order, total;
+    size_t cs32, v32, cs64, order, best_key, total;
 };
 
-int64_t padded_hyp(int32_t n_hyp) { return ((int64_t)n_hyp + kHypGroup - 1) / kHypGroup * kHypGroup; }
-
-Layout make_layout(int64_t n_clusters, int64_t n_points, int32_t n_hyp) {
+Layout make_layout(int64_t n_clusters, int64_t n_points) {
     Layout L;
     const size_t np = (size_t)n_points;
-    const size_t nq = (size_t)n_clusters * (size_t)n_hyp;
     size_t at = 0;
-    L.c32 = at; at = align_up(at + np * sizeof(float));
-    L.s32 = at; at = align_up(at + np * sizeof(float));
+    L.cs32 = at; at = align_up(at + np * sizeof(float2));
     L.v32 = at; at = align_up(at + np * sizeof(float));
-    L.c64 = at; at = align_up(at + np * sizeof(double));
-    L.s64 = at; at = align_up(at + np * sizeof(double));
-    const size_t nq_pad = (size_t)n_clusters * (size_t)padded_hyp(n_hyp);
-    L.hyp = at; at = align_up(at + nq_pad * sizeof(float2));
-    L.valid = at; at = align_up(at + nq * sizeof(uint8_t));
-    L.counts = at; at = align_up(at + nq * sizeof(int32_t));
+    L.cs64 = at; at = align_up(at + np * sizeof(double2));
     L.order = at; at = align_up(at + (size_t)n_clusters * sizeof(int32_t));
+    L.best_key = at; at = align_up(at + (size_t)n_clusters * sizeof(unsigned long long));
     L.total = at;
     return L;
 }
 
 // Stage timing: events recorded around each kernel of each call.
-constexpr int kStages = 4;
+constexpr int kStages = 3;
 struct TimedCall {
     hipEvent_t ev[kStages + 1];
 };
@@ -588,7 +598,7 @@ extern "C" {
 
 size_t rv_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t n_hyp) {
     if (n_clusters < 0 || n_points < 0 || n_hyp < 0) return 0;
-    return make_layout(n_clusters, n_points, n_hyp).total;
+    return make_layout(n_clusters, n_points).total;
 }
 
 const char *rv_last_error(void) { return g_error; }
@@ -614,13 +624,11 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
         (vx == nullptr || vy == nullptr || heading == nullptr || n_inliers == nullptr ||
          status == nullptr))
         return fail(RV_ERR_INVALID_ARG, "a required output is NULL");
-    const int64_t n_hyp_pad = padded_hyp(n_hyp);
-    const int64_t score_bpc = ((int64_t)n_hyp + kHypPerBlock - 1) / kHypPerBlock;
-    const int64_t hyp_bpc = (n_hyp_pad + kBlock - 1) / kBlock;
+    const int64_t blocks_per_cluster = ((int64_t)n_hyp + kScoreBlock - 1) / kScoreBlock;
     const int64_t clusters_xcd = (n_clusters + kXcds - 1) / kXcds * kXcds;
-    if (clusters_xcd > (int64_t)INT32_MAX / hyp_bpc)
+    if (clusters_xcd > (int64_t)INT32_MAX / blocks_per_cluster)
         return fail(RV_ERR_INVALID_ARG, "n_clusters * ceil(n_hyp / 256) exceeds 2^31 - 1");
-    const Layout L = make_layout(n_clusters, n_points, n_hyp);
+    const Layout L = make_layout(n_clusters, n_points);
     if (workspace == nullptr || workspace_bytes < L.total)
         return fail(RV_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
                     workspace == nullptr ? (size_t)0 : workspace_bytes);
@@ -629,15 +637,16 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     if (n_clusters == 0) return RV_OK;
 
     char *ws = (char *)workspace;
-    float *c32 = (float *)(ws + L.c32);
-    float *s32 = (float *)(ws + L.s32);
+    float2 *cs32 = (float2 *)(ws + L.cs32);
     float *v32 = (float *)(ws + L.v32);
-    double *c64 = (double *)(ws + L.c64);
-    double *s64 = (double *)(ws + L.s64);
-    float2 *hyp = (float2 *)(ws + L.hyp);
-    uint8_t *valid = (uint8_t *)(ws + L.valid);
-    int32_t *counts = hyp_counts != nullptr ? hyp_counts : (int32_t *)(ws + L.counts);
-    int32_t *order = (int32_t *)(ws + L.order);
+    double2 *cs64 = (double2 *)(ws + L.cs64);
+    Points pts;
+    pts.cs32 = cs32;
+    pts.v32 = v32;
+    pts.cs64 = cs64;
+    pts.theta = theta;
+    int32_t *order = n_clusters <= kPlanMaxClusters ? (int32_t *)(ws + L.order) : nullptr;
+    unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
     const uint32_t key0 = (uint32_t)(seed & 0xFFFFFFFFu), key1 = (uint32_t)(seed >> 32);
     const int64_t n_words = inlier_bits != nullptr ? (n_points + 31) / 32 : 0;
     hipStream_t st = (hipStream_t)stream;
@@ -645,30 +654,33 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     TimedCall tc;
     const bool timed = take_timed_call(tc);
     if (timed) (void)hipEventRecord(tc.ev[0], st);
-
-    const int64_t prep_items = n_points > n_words ? n_points : n_words;
-    if (prep_items > 0)
-        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)((prep_items + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, st, theta, vd, n_points, c32, s32, v32, c64, s64,
-                           inlier_bits, n_words);
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanBlock), 0, st, cluster_offsets,
-                       n_clusters, n_points, order);
+    int64_t prep_items = n_points > n_words ? n_points : n_words;
+    prep_items = prep_items > n_clusters ? prep_items : n_clusters;
+    const int64_t prep_blocks = (prep_items + kPrepBlock - 1) / kPrepBlock + 1;  // + planner
+    hipLaunchKernelGGL(prep_kernel, dim3((unsigned)prep_blocks), dim3(kPrepBlock), 0, st, theta,
+                       vd, n_points, cs32, v32, cs64, inlier_bits, n_words, cluster_offsets,
+                       n_clusters, order, best_key);
     if (timed) (void)hipEventRecord(tc.ev[1], st);
-    hipLaunchKernelGGL(hyp_kernel, dim3((unsigned)(n_clusters * hyp_bpc)), dim3(kBlock), 0, st,
-                       theta, vd, cluster_offsets, n_points, n_hyp, (int32_t)n_hyp_pad,
-                       (int32_t)hyp_bpc, key0, key1, c64, s64, hyp, valid);
+    hipLaunchKernelGGL(score_kernel, dim3((unsigned)(clusters_xcd * blocks_per_cluster)),
+                       dim3(kScoreBlock), 0, st, cluster_offsets, (const int32_t *)order,
+                       n_clusters, n_points, n_hyp, (int32_t)blocks_per_cluster, key0, key1,
+                       pts, tau, best_key, hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
-    hipLaunchKernelGGL(score_kernel, dim3((unsigned)(clusters_xcd * score_bpc)), dim3(kBlock), 0,
-                       st, cluster_offsets, (const int32_t *)order, n_clusters, n_points, n_hyp,
-                       (int32_t)n_hyp_pad, (int32_t)score_bpc, c32, s32, v32,
-                       (const float2 *)hyp, tau, counts);
-    if (timed) (void)hipEventRecord(tc.ev[3], st);
-    hipLaunchKernelGGL(refit_kernel, dim3((unsigned)n_clusters), dim3(kBlock), 0, st,
-                       cluster_offsets, n_points, n_hyp, key0, key1, theta, vd, c64, s64,
-                       (const int32_t *)counts, (const uint8_t *)valid, (double)tau, vx, vy,
-                       heading, n_inliers, status, n_near_tau, inlier_bits, best_hyp);
+    Outputs o;
+    o.vx = vx;
+    o.vy = vy;
+    o.heading = heading;
+    o.n_inliers = n_inliers;
+    o.status = status;
+    o.n_near = n_near_tau;
+    o.best = best_hyp;
+    o.hyp_counts = hyp_counts;
+    o.bits = inlier_bits;
+    hipLaunchKernelGGL(refit_kernel, dim3((unsigned)n_clusters), dim3(kRefitBlock), 0, st,
+                       cluster_offsets, (const int32_t *)order, n_points, key0, key1,
+                       pts, (const unsigned long long *)best_key, tau, o);
     if (timed) {
-        (void)hipEventRecord(tc.ev[4], st);
+        (void)hipEventRecord(tc.ev[3], st);
         keep_timed_call(tc);
     }
     const hipError_t e = hipGetLastError();
@@ -688,7 +700,7 @@ int rv_stage_times(double *ms, int64_t *n_calls) {
         std::lock_guard<std::mutex> lock(g_timing_mutex);
         calls.swap(g_pending);
     }
-    double sum[kStages] = {0.0, 0.0, 0.0, 0.0};
+    double sum[kStages] = {0.0, 0.0, 0.0};
     int rc = RV_OK;
     for (const TimedCall &tc : calls) {
         if (hipEventSynchronize(tc.ev[kStages]) != hipSuccess) {
@@ -721,9 +733,9 @@ int rv_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out, in
     if (n == 0) return RV_OK;
     if (ctr == nullptr || key == nullptr || out == nullptr)
         return fail(RV_ERR_INVALID_ARG, "a pointer is NULL");
-    const int64_t grid = (n + kBlock - 1) / kBlock;
+    const int64_t grid = (n + kPrepBlock - 1) / kPrepBlock;
     if (grid > INT32_MAX) return fail(RV_ERR_INVALID_ARG, "n too large");
-    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)grid), dim3(kBlock), 0,
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)grid), dim3(kPrepBlock), 0,
                        (hipStream_t)stream, ctr, key, out, n);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
