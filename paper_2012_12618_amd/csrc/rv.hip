@@ -70,11 +70,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1
             k0 += kPhiloxW0;
             k1 += kPhiloxW1;
         }
-        const uint32_t hi0 = __umulhi(kPhiloxM0, x.x);
-        const uint32_t lo0 = kPhiloxM0 * x.x;
-        const uint32_t hi1 = __umulhi(kPhiloxM1, x.z);
-        const uint32_t lo1 = kPhiloxM1 * x.z;
-        x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+        // one 32x32->64 multiply-add instruction per product
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * x.x;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * x.z;
+        x = make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ x.w ^ k1, (uint32_t)p0);
     }
     return x;
 }
@@ -83,8 +83,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1
 // the second index skips the first).  Requires 2 <= n < 2^31.
 __device__ __forceinline__ void seed_pair(uint32_t u0, uint32_t u1, uint32_t n, uint32_t &i,
                                           uint32_t &j) {
-    i = __umulhi(u0, n);
-    const uint32_t b = __umulhi(u1, n - 1u);
+    i = (uint32_t)(((uint64_t)u0 * n) >> 32);
+    const uint32_t b = (uint32_t)(((uint64_t)u1 * (n - 1u)) >> 32);
     j = b + (b >= i ? 1u : 0u);
 }
 
