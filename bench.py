@@ -31,17 +31,21 @@ WORKLOAD_TEXT = {
               "U[-40,40], 15% micro-Doppler band +/-[0.5,2]|v|), 1024 hypotheses, tau 0.15 m/s, FP32"),
     "small": ("small frame: 64 clusters of U{20..200} points, 20% uniform outliers, "
               "256 hypotheses, tau 0.15 m/s, FP32"),
+    "batched": ("batched form: 256 frames of U{100..1500} clusters, log-uniform [8, 2048] points, "
+                "20% uniform outliers, 512 hypotheses, tau 0.15 m/s, FP32; one captured HIP graph "
+                "(staging, size-class ordering, persistent work-queue scoring, refit) per step"),
 }
+FRAME_WORKLOADS = ("dense", "small")
 
 
-def profiled_traffic(workload: str):
+def profiled_traffic(workload: str, kernel: str = "score_kernel"):
     """HBM bytes per scoring launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a copy of known size), or None
     when there is none for this workload or the kernel source changed since."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", f"score_kernel_{workload}_frame_counters.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     src = os.path.join(ROOT, "paper_2012_12618_amd", "csrc", "rv.hip")
     if not os.path.exists(path):
         return None
@@ -62,6 +66,162 @@ def percentile(xs, q):
     return xs[i]
 
 
+def oracle_baseline(frames, n_hyp, tau, seed_of, threads, budget_s=1.5, max_frames=64):
+    """The FP64 oracle on whole frames (fresh seeds) until about budget_s of wall time."""
+    import oracle
+
+    done, dt, evals, clusters = 0, 0.0, 0, 0
+    while done == 0 or (dt < budget_s and done < max_frames):
+        f = frames[done % len(frames)]
+        t0 = time.perf_counter()
+        oracle.estimate_velocity(f.theta, f.vd, f.offsets, n_hyp, tau, seed_of(done),
+                                 want_mask=False, n_threads=threads)
+        dt += time.perf_counter() - t0
+        evals += sum_evals(f, n_hyp)
+        clusters += f.n_clusters
+        done += 1
+    return done, dt, evals, clusters
+
+
+def sum_evals(frame, n_hyp):
+    from paper_2012_12618_amd import synth
+
+    return synth.evals_per_frame(frame.offsets, n_hyp)
+
+
+def batch_bench(args, torch, binding, synth, dev) -> int:
+    """Batched form: every step replays one captured graph over all frames."""
+    name = args.workload
+    print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)
+    batch, n_hyp, tau = synth.make_batch_workload(name, n_frames=args.frames or None)
+    fr = batch.frame
+    F, K, N = batch.n_frames, fr.n_clusters, fr.n_points
+    evals = synth.evals_per_frame(fr.offsets, n_hyp)
+    theta = torch.from_numpy(fr.theta).to(dev)
+    vd = torch.from_numpy(fr.vd).to(dev)
+    offsets = torch.from_numpy(fr.offsets).to(dev)
+    fo = torch.from_numpy(batch.frame_offsets).to(dev)
+    seeds = torch.from_numpy(batch.seeds.view("int64")).to(dev)
+    tuning = None
+    if args.tuning:
+        from paper_2012_12618_amd import tuner
+
+        tuning = tuner.load(args.tuning, torch.cuda.get_device_name(dev), n_hyp)
+    out = binding.allocate_batch_outputs(F, K, N, n_hyp, dev, want_near=True)
+    stream = torch.cuda.current_stream(dev)
+    graph = binding.rv_graph_capture_batch(theta, vd, offsets, fo, seeds, n_hyp, tau, out,
+                                           tuning=tuning)
+
+    def step():
+        seeds.add_(1)  # fresh hypothesis seeds for every frame of every step
+        graph.launch(stream)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    print(f"[bench] timing {args.steps} graph steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    graph.destroy()
+
+    # Per-kernel durations: the same launch sequence called eagerly with the
+    # library's events around each kernel.
+    print(f"[bench] kernel timing over {args.steps} eager calls", file=sys.stderr, flush=True)
+    binding.rv_stage_times()
+    binding.rv_stage_timing(True)
+    for _ in range(args.steps):
+        seeds.add_(1)
+        binding.rv_estimate_velocity_batch(theta, vd, offsets, fo, seeds, n_hyp, tau,
+                                           tuning=tuning, out=out, stream=stream)
+    torch.cuda.synchronize()
+    binding.rv_stage_timing(False)
+    stage_ms, n_calls = binding.rv_stage_times()
+    stage_avg = [x / max(n_calls, 1) for x in stage_ms]
+    score_ms = stage_avg[binding.STAGE_NAMES.index("score")]
+    achieved_tflops = FLOP_PER_EVAL * evals / (score_ms / 1e3) / 1e12
+
+    # The plain per-frame form on the same frames, one call per frame.
+    print("[bench] per-frame form on the same frames", file=sys.stderr, flush=True)
+    per = []
+    for f in range(F):
+        s = batch.frame_slice(f)
+        t_ = (torch.from_numpy(s.theta).to(dev), torch.from_numpy(s.vd).to(dev),
+              torch.from_numpy(s.offsets).to(dev))
+        per.append((t_, int(batch.seeds[f]), binding.allocate_outputs(s.n_clusters, s.n_points, n_hyp, dev)))
+
+    def per_frame_pass(salt):
+        for (t_, v_, o_), seed, o2 in per:
+            binding.rv_estimate_velocity(t_, v_, o_, n_hyp, tau, (seed + salt) & (2**64 - 1), out=o2,
+                                         stream=stream)
+
+    per_frame_pass(0)
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 5))
+    ev0.record(stream)
+    for r in range(reps):
+        per_frame_pass(r + 1)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    per_frame_ms = ev0.elapsed_time(ev1) / reps
+    del per
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        print(f"[bench] oracle on the host, {threads} threads", file=sys.stderr, flush=True)
+        sample = [batch.frame_slice(f) for f in range(min(F, 8))]
+        done, dt, ev_done, cl_done = oracle_baseline(
+            sample, n_hyp, tau, lambda i: synth.frame_seed(name, 50_000 + i), threads)
+        cpu = {"value": ev_done / dt, "unit": "hyp-point evals/s", "cores": threads, "kind": "oracle",
+               "sample": (f"{done} whole frame(s) of the batch ({cl_done} clusters, {ev_done} evals), "
+                          f"FP64, {dt:.2f} s wall on {threads} threads"),
+               "clusters_per_s": cl_done / dt}
+
+    sec = ms_per_step / 1e3
+    line = {
+        "metric": METRIC,
+        "value": evals / sec,
+        "unit": "hyp-point evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[name], "frames": F, "clusters": K, "points": N,
+                   "n_hyp": n_hyp, "tau": tau, "evals_per_step": evals,
+                   "tuning": tuning.to_dict() if tuning is not None else "default"},
+        "clusters_per_s": K / sec,
+        "frac_fp32_valu_peak": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+        "per_frame_form": {"ms_per_batch": per_frame_ms, "clusters_per_s": K / (per_frame_ms / 1e3),
+                           "evals_per_s": evals / (per_frame_ms / 1e3),
+                           "scope": "rv_estimate_velocity once per frame, same frames, one stream"},
+        "stage_ms": dict(zip(binding.STAGE_NAMES, stage_avg)),
+        "wall_ms_per_step": wall * 1e3 / args.steps,
+        "roofline": {"bound": "alu", "kernel": "batch_score_kernel", "achieved": achieved_tflops,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": profiled_traffic(name, "batch_score_kernel"),
+                     "algorithmic_flop_per_launch": FLOP_PER_EVAL * evals,
+                     "kernel_ms": score_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +232,11 @@ def main() -> int:
                     help="frames timed from pinned host memory to results in host memory")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: min(16, cpus))")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="batched workload: number of frames (0: the workload's 256)")
+    ap.add_argument("--tuning", default="",
+                    help="batched workload: JSON tuning table written by paper_2012_12618_amd.tuner "
+                         "(default: the library's default setting)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (outside the timed "
                          "region), the reference kernel for scaling HBM byte counters")
@@ -96,6 +261,8 @@ def main() -> int:
     binding.load_library()
     dev = torch.device("cuda:0")
     name = args.workload
+    if name not in FRAME_WORKLOADS:
+        return batch_bench(args, torch, binding, synth, dev)
     print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)
     frame, n_hyp, tau = synth.make_workload(name)
     K, N = frame.n_clusters, frame.n_points

@@ -110,14 +110,83 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
                          int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/*
+ * ---- Many frames at once ---------------------------------------------------
+ *
+ * The frames share one CSR: frame f owns clusters [frame_offsets[f],
+ * frame_offsets[f+1]) of cluster_offsets (frame_offsets[0] = 0, non-decreasing,
+ * frame_offsets[n_frames] = n_clusters).  Cluster k of frame f draws its
+ * hypotheses with key = (seeds[f] & 0xffffffff, seeds[f] >> 32) and counter =
+ * (h, k - frame_offsets[f], 0, 0): every cluster's outputs are bitwise those
+ * rv_estimate_velocity gives for its frame alone with seed seeds[f].  The
+ * scoring runs as one persistent launch that drains a device work queue of
+ * (cluster, block of 256 hypotheses) items, largest clusters first.
+ */
+
+/* Cluster-size buckets of the tuning table: bucket 0 holds n < 64, bucket b
+   holds 32 * 2^b <= n < 64 * 2^b, bucket RV_TUNE_BUCKETS - 1 everything larger. */
+#define RV_TUNE_BUCKETS 8
+
+typedef struct {
+    /* register rows of 64 points scored per pass, 1..16, per size bucket */
+    int32_t rows_max[RV_TUNE_BUCKETS];
+    /* persistent scoring grid: workgroups per compute unit; 0 = as many as fit */
+    int32_t blocks_per_cu;
+} rv_tuning_t;
+
+/* Defaults: 16 rows in every bucket, as many workgroups per CU as fit. */
+void rv_tuning_default(rv_tuning_t *tuning);
+
+/* Device workspace bytes of rv_estimate_velocity_batch (0 for invalid sizes). */
+size_t rv_batch_workspace_bytes(int64_t n_frames, int64_t n_clusters, int64_t n_points,
+                                int32_t n_hyp);
+
+/*
+ * rv_estimate_velocity over n_frames >= 1 frames in one launch sequence.
+ * Arguments as rv_estimate_velocity, plus:
+ *   frame_offsets[n_frames + 1]  int32, device: the frames' cluster ranges;
+ *   seeds[n_frames]              uint64, device: each frame's hypothesis seed;
+ *   tuning                       host struct, nullable (defaults), read during the call.
+ * Inconsistent frame offsets are never a memory error (a cluster is then
+ * attributed to some frame in [0, n_frames)).  The workspace must hold
+ * rv_batch_workspace_bytes(n_frames, n_clusters, n_points, n_hyp) bytes.
+ */
+int rv_estimate_velocity_batch(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                               const int32_t *frame_offsets, const uint64_t *seeds,
+                               int64_t n_frames, int64_t n_clusters, int64_t n_points,
+                               int32_t n_hyp, float tau, float *vx, float *vy, float *heading,
+                               int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
+                               uint32_t *inlier_bits, int32_t *hyp_counts, int32_t *best_hyp,
+                               const rv_tuning_t *tuning, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/*
+ * HIP graph of one rv_estimate_velocity_batch call.  Capture records the
+ * launch sequence with these pointers and sizes (on a private stream; nothing
+ * runs); the caller keeps every buffer alive and in place while the graph
+ * exists, and may change their contents between launches.  rv_graph_launch
+ * replays it on `stream`; replays on one stream are ordered, replays that share
+ * a workspace must not overlap.  The graph holds no HIP memset nodes.
+ */
+typedef struct rv_graph rv_graph_t;
+int rv_graph_capture_batch(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                           const int32_t *frame_offsets, const uint64_t *seeds, int64_t n_frames,
+                           int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau,
+                           float *vx, float *vy, float *heading, int32_t *n_inliers,
+                           uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                           int32_t *hyp_counts, int32_t *best_hyp, const rv_tuning_t *tuning,
+                           void *workspace, size_t workspace_bytes, rv_graph_t **graph);
+int rv_graph_launch(rv_graph_t *graph, void *stream);
+void rv_graph_destroy(rv_graph_t *graph);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *rv_last_error(void);
 
 /*
  * Instrumentation (not part of the estimate).  While enabled, every
- * rv_estimate_velocity call records HIP events around each of its three
- * kernels on its stream.  rv_stage_times waits for the recorded events, writes
- * the summed milliseconds per kernel (ms[0]: point staging and dispatch
+ * rv_estimate_velocity or rv_estimate_velocity_batch call (not graph replays)
+ * records HIP events around its kernels on its stream.  rv_stage_times waits for the recorded events, writes
+ * the summed milliseconds per stage (ms[0]: point staging and dispatch
  * planning, ms[1]: hypotheses and scoring, ms[2]: selection and refit) and the
  * number of calls into *n_calls, and clears the record.  Returns RV_OK or
  * RV_ERR_HIP.

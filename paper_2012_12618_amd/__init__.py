@@ -13,6 +13,8 @@ from importlib import import_module
 _BINDING_NAMES = (
     "rv_estimate_velocity", "rv_workspace_bytes", "rv_last_error", "rv_stage_timing",
     "rv_stage_times", "rv_philox4x32_10", "allocate_outputs", "load_library", "RVError",
+    "rv_tuning_default", "rv_batch_workspace_bytes", "rv_estimate_velocity_batch",
+    "rv_graph_capture_batch", "allocate_batch_outputs", "RVTuning", "RVGraph",
 )
 
 __all__ = list(_BINDING_NAMES)

@@ -29,10 +29,30 @@ RV_MIN_SEED_SEPARATION = 1e-3
 RV_NEAR_TAU_WINDOW = 1e-5
 RV_MAX_HYP = 1 << 20
 
+RV_TUNE_BUCKETS = 8
+
 N_STAGES = 3
 STAGE_NAMES = ("prep", "score", "refit")
 
 _lib = None
+
+
+class RVTuning(ctypes.Structure):
+    """rv_tuning_t: register rows per pass for each cluster-size bucket and the
+    persistent grid's workgroups per compute unit (0: as many as fit)."""
+
+    _fields_ = [("rows_max", ctypes.c_int32 * RV_TUNE_BUCKETS), ("blocks_per_cu", ctypes.c_int32)]
+
+    def to_dict(self) -> dict:
+        return {"rows_max": list(self.rows_max), "blocks_per_cu": int(self.blocks_per_cu)}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "RVTuning":
+        t = cls()
+        for i, r in enumerate(d["rows_max"]):
+            t.rows_max[i] = int(r)
+        t.blocks_per_cu = int(d.get("blocks_per_cu", 0))
+        return t
 
 
 class RVError(RuntimeError):
@@ -68,6 +88,20 @@ def load_library() -> ctypes.CDLL:
     lib.rv_stage_times.argtypes = [P, P]
     lib.rv_philox4x32_10.restype = ctypes.c_int
     lib.rv_philox4x32_10.argtypes = [P, P, P, i64, P]
+    lib.rv_tuning_default.restype = None
+    lib.rv_tuning_default.argtypes = [P]
+    lib.rv_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.rv_batch_workspace_bytes.argtypes = [i64, i64, i64, i32]
+    batch_args = [P, P, P, P, P, i64, i64, i64, i32, ctypes.c_float,
+                  P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t]
+    lib.rv_estimate_velocity_batch.restype = ctypes.c_int
+    lib.rv_estimate_velocity_batch.argtypes = batch_args + [P]
+    lib.rv_graph_capture_batch.restype = ctypes.c_int
+    lib.rv_graph_capture_batch.argtypes = batch_args + [P]
+    lib.rv_graph_launch.restype = ctypes.c_int
+    lib.rv_graph_launch.argtypes = [P, P]
+    lib.rv_graph_destroy.restype = None
+    lib.rv_graph_destroy.argtypes = [P]
     _lib = lib
     return lib
 
@@ -202,3 +236,130 @@ def rv_philox4x32_10(ctr: torch.Tensor, key: torch.Tensor,
                                 ctypes.c_void_p(out.data_ptr()), n,
                                 ctypes.c_void_p(stream.cuda_stream)))
     return out
+
+
+# ---- many frames ------------------------------------------------------------
+
+def rv_tuning_default() -> RVTuning:
+    t = RVTuning()
+    load_library().rv_tuning_default(ctypes.byref(t))
+    return t
+
+
+def rv_batch_workspace_bytes(n_frames: int, n_clusters: int, n_points: int, n_hyp: int) -> int:
+    return int(load_library().rv_batch_workspace_bytes(int(n_frames), int(n_clusters),
+                                                       int(n_points), int(n_hyp)))
+
+
+def allocate_batch_outputs(n_frames: int, n_clusters: int, n_points: int, n_hyp: int, device, *,
+                           want_near: bool = True, want_bits: bool = False,
+                           debug: bool = False) -> dict:
+    """Outputs and workspace for rv_estimate_velocity_batch / rv_graph_capture_batch."""
+    out = allocate_outputs(n_clusters, n_points, n_hyp, device, want_near=want_near,
+                           want_bits=want_bits, debug=debug)
+    out["workspace"] = torch.empty(
+        max(rv_batch_workspace_bytes(n_frames, n_clusters, n_points, n_hyp), 1),
+        dtype=torch.uint8, device=torch.device(device))
+    return out
+
+
+def _batch_args(theta, vd, offsets, frame_offsets, seeds, n_hyp, tau, out, tuning):
+    device = theta.device
+    if device.type != "cuda":
+        raise ValueError("theta must be a GPU tensor")
+    n_points = int(theta.numel())
+    n_clusters = int(offsets.numel()) - 1
+    n_frames = int(frame_offsets.numel()) - 1
+    if n_clusters < 0 or n_frames < 1:
+        raise ValueError("offsets needs n_clusters + 1 entries, frame_offsets n_frames + 1 >= 2")
+    if int(vd.numel()) != n_points:
+        raise ValueError("theta and vd differ in length")
+    if int(seeds.numel()) != n_frames:
+        raise ValueError("seeds needs one entry per frame")
+    ws = out["workspace"]
+    tune = tuning if tuning is not None else rv_tuning_default()
+    args = [
+        _dev_ptr(theta, torch.float32, device, "theta"),
+        _dev_ptr(vd, torch.float32, device, "vd"),
+        _dev_ptr(offsets, torch.int32, device, "offsets"),
+        _dev_ptr(frame_offsets, torch.int32, device, "frame_offsets"),
+        _dev_ptr(seeds, torch.int64, device, "seeds"),
+        n_frames, n_clusters, n_points, int(n_hyp), float(tau),
+        _dev_ptr(out["vx"], torch.float32, device, "vx"),
+        _dev_ptr(out["vy"], torch.float32, device, "vy"),
+        _dev_ptr(out["heading"], torch.float32, device, "heading"),
+        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
+        _dev_ptr(out["status"], torch.uint8, device, "status"),
+        _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau"),
+        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
+        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
+        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+        ctypes.byref(tune),
+        ctypes.c_void_p(ws.data_ptr()), int(ws.numel()),
+    ]
+    return args, tune
+
+
+def rv_estimate_velocity_batch(theta, vd, offsets, frame_offsets, seeds, n_hyp: int, tau: float, *,
+                               tuning: RVTuning | None = None, want_near: bool = True,
+                               want_bits: bool = False, debug: bool = False,
+                               out: dict | None = None, stream=None) -> dict:
+    """Per-cluster outputs of n_frames frames in one launch sequence.
+
+    ``frame_offsets``: int32 [n_frames + 1] cluster ranges of the frames;
+    ``seeds``: int64 [n_frames] (bit patterns of the uint64 seeds), on the GPU.
+    Every cluster's outputs equal rv_estimate_velocity on its frame alone.
+    """
+    lib = load_library()
+    n_points = int(theta.numel())
+    n_clusters = int(offsets.numel()) - 1
+    n_frames = int(frame_offsets.numel()) - 1
+    if out is None:
+        out = allocate_batch_outputs(n_frames, n_clusters, n_points, n_hyp, theta.device,
+                                     want_near=want_near, want_bits=want_bits, debug=debug)
+    args, _tune = _batch_args(theta, vd, offsets, frame_offsets, seeds, n_hyp, tau, out, tuning)
+    if stream is None:
+        stream = torch.cuda.current_stream(theta.device)
+    _check(lib.rv_estimate_velocity_batch(*args, ctypes.c_void_p(stream.cuda_stream)))
+    return {k: v for k, v in out.items() if k != "workspace"}
+
+
+class RVGraph:
+    """A captured rv_estimate_velocity_batch launch sequence (HIP graph).
+
+    Keeps references to every tensor it was captured with: their contents may
+    change between launches, their storage may not.
+    """
+
+    def __init__(self, handle, tensors):
+        self._handle = handle
+        self._tensors = tensors
+
+    def launch(self, stream=None) -> None:
+        if self._handle is None:
+            raise RuntimeError("graph destroyed")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(load_library().rv_graph_launch(self._handle, ctypes.c_void_p(stream.cuda_stream)))
+
+    def destroy(self) -> None:
+        if self._handle is not None:
+            load_library().rv_graph_destroy(self._handle)
+            self._handle = None
+            self._tensors = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def rv_graph_capture_batch(theta, vd, offsets, frame_offsets, seeds, n_hyp: int, tau: float,
+                           out: dict, *, tuning: RVTuning | None = None) -> RVGraph:
+    """Capture one batched estimate into a HIP graph (nothing runs until launch)."""
+    lib = load_library()
+    args, tune = _batch_args(theta, vd, offsets, frame_offsets, seeds, n_hyp, tau, out, tuning)
+    handle = ctypes.c_void_p()
+    _check(lib.rv_graph_capture_batch(*args, ctypes.byref(handle)))
+    return RVGraph(handle, (theta, vd, offsets, frame_offsets, seeds, out, tune))

@@ -284,16 +284,18 @@ __device__ __forceinline__ uint32_t score_rows(const float2 *__restrict__ cs_chu
 }
 
 // Inlier counts of the wave's nh hypotheses (LDS at hp) over all points of the
-// cluster; lane q returns the count of hypothesis q.
-__device__ __forceinline__ uint32_t score_cluster(const Points &pts, Span sp,
-                                                  int lane, const float4 *hp, int nh,
-                                                  float tau) {
+// cluster, rows_max (<= kRowsMax) register rows of points per pass; lane q
+// returns the count of hypothesis q.
+__device__ __forceinline__ uint32_t score_cluster(const Points &pts, Span sp, int lane,
+                                                  const float4 *hp, int nh, float tau,
+                                                  int rows_max) {
     const int ng = (nh + kHypGroup - 1) / kHypGroup;
     const int64_t end = sp.lo + sp.n;
+    const int64_t pass = (int64_t)rows_max * kWave;
     uint32_t total = 0;
-    for (int64_t base = sp.lo; base < end; base += (int64_t)kRowsMax * kWave) {
+    for (int64_t base = sp.lo; base < end; base += pass) {
         const int64_t left = end - base;
-        const int npts = (int)(left < (int64_t)kRowsMax * kWave ? left : (int64_t)kRowsMax * kWave);
+        const int npts = (int)(left < pass ? left : pass);
         const int rows = (npts + kWave - 1) / kWave;
         const float2 *cs_chunk = pts.cs32 + base;
         const float *v_chunk = pts.v32 + base;
@@ -308,6 +310,68 @@ __device__ __forceinline__ uint32_t score_cluster(const Points &pts, Span sp,
         }
     }
     return total;
+}
+
+// A cluster's hypotheses: Philox key and the cluster index of the counter
+// (the cluster's index within its own frame), and the index of its outputs.
+struct ClusterId {
+    int64_t out;       // index into the per-cluster outputs
+    uint32_t local;    // counter word 1 of its hypotheses
+    uint32_t key0, key1;
+};
+
+// One scoring block: hypotheses [b * 256, b * 256 + 256) of one cluster.  Each
+// thread draws and solves one hypothesis into LDS; each wave then scores 64 of
+// them against every point of the cluster.  The block's best (count, lowest
+// index) key over its valid hypotheses is merged into best_key with a 64-bit
+// atomic maximum, whose result does not depend on the order of the blocks.
+// Called by all threads of the block; contains block barriers.
+__device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_t n_hyp,
+                                            const Points &pts, float tau, int rows_max,
+                                            float4 *s_hyp, unsigned long long *s_key,
+                                            unsigned long long *__restrict__ best_key,
+                                            int32_t *__restrict__ hyp_counts) {
+    const int tid = threadIdx.x;
+    const int64_t h = (int64_t)b * kScoreBlock + tid;
+    if (!sp.ok || sp.n < 2) {
+        if (hyp_counts != nullptr && h < n_hyp) hyp_counts[id.out * n_hyp + h] = 0;
+        return;
+    }
+    {
+        float hx = __builtin_nanf(""), hy = __builtin_nanf("");
+        if (h < n_hyp) {
+            const Hypothesis hyp = make_hypothesis(pts, sp, (uint32_t)h, id.local, id.key0, id.key1);
+            hx = (float)hyp.vx;  // NaN exactly when the pair is degenerate
+            hy = (float)hyp.vy;
+        }
+        reinterpret_cast<float2 *>(s_hyp)[tid] = make_float2(hx, hy);
+    }
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = tid % kWave;
+    const int64_t h0 = (int64_t)b * kScoreBlock + wave * kWave;
+    unsigned long long key = 0;
+    if (h0 < n_hyp) {
+        const int nh = (int64_t)n_hyp - h0 < kWave ? (int)((int64_t)n_hyp - h0) : kWave;
+        const uint32_t cnt =
+            score_cluster(pts, sp, lane, s_hyp + wave * (kWave / 2), nh, tau, rows_max);
+        // The lane's own hypothesis is re-read from LDS rather than kept in
+        // registers through the scoring loop.
+        const int64_t hl = h0 + lane;
+        if (lane < nh) {
+            if (hyp_counts != nullptr) hyp_counts[id.out * n_hyp + hl] = (int32_t)cnt;
+            if (!__builtin_isnan(reinterpret_cast<const float2 *>(s_hyp)[tid].x))
+                key = ((unsigned long long)cnt << 32) | (0xFFFFFFFFull - (uint32_t)hl);
+        }
+    }
+    key = wave_max_u64(key);
+    if (lane == 0) s_key[wave] = key;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kScoreBlock / kWave; ++w) key = s_key[w] > key ? s_key[w] : key;
+        if (key != 0) atomicMax(&best_key[id.out], key);
+    }
 }
 
 struct Outputs {
@@ -329,99 +393,28 @@ __device__ __forceinline__ void write_failed(const Outputs &o, int64_t k, uint8_
     if (o.best) o.best[k] = -1;
 }
 
-// Work item = (cluster, block of 256 hypotheses).  Block i takes the item that
-// keeps clusters in the planned order while all items of one cluster run on the
-// same XCD (blocks are dealt to the 8 XCDs round-robin), sharing that XCD's L2
-// copy of the cluster's points.  Each thread first draws and solves one
-// hypothesis into LDS; each wave then scores 64 of them against every point of
-// the cluster.  The block's best (count, lowest index) key over its valid
-// hypotheses is merged into best_key[k] with a 64-bit atomic maximum, whose
-// result does not depend on the order of the blocks.
-// Eight waves per SIMD: the scoring loop fits in 64 VGPRs.
-__global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))) void score_kernel(
-    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
-    int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster, uint32_t key0, uint32_t key1,
-    Points pts, float tau, unsigned long long *__restrict__ best_key,
-    int32_t *__restrict__ hyp_counts) {
-    __shared__ float4 s_hyp[kScoreBlock / 2];  // (vx, vy) pairs, two per float4
-    __shared__ unsigned long long s_key[kScoreBlock / kWave];
-    const uint32_t xcd = blockIdx.x % kXcds;
-    const uint32_t r = blockIdx.x / kXcds;
-    const int64_t j = xcd + (int64_t)kXcds * (r / (uint32_t)blocks_per_cluster);
-    if (j >= n_clusters) return;
-    const int b = (int)(r % (uint32_t)blocks_per_cluster);
-    const int64_t k = order != nullptr ? order[j] : j;
-    const int tid = threadIdx.x;
-    const int64_t h = (int64_t)b * kScoreBlock + tid;
-    const Span sp = cluster_span(off, k, n_points);
-    if (!sp.ok || sp.n < 2) {
-        if (hyp_counts != nullptr && h < n_hyp) hyp_counts[k * n_hyp + h] = 0;
-        return;
-    }
-
-    {
-        float hx = __builtin_nanf(""), hy = __builtin_nanf("");
-        if (h < n_hyp) {
-            const Hypothesis hyp = make_hypothesis(pts, sp, (uint32_t)h, (uint32_t)k, key0, key1);
-            hx = (float)hyp.vx;  // NaN exactly when the pair is degenerate
-            hy = (float)hyp.vy;
-        }
-        reinterpret_cast<float2 *>(s_hyp)[tid] = make_float2(hx, hy);
-    }
-    __syncthreads();
-
-    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int lane = tid % kWave;
-    const int64_t h0 = (int64_t)b * kScoreBlock + wave * kWave;
-    unsigned long long key = 0;
-    if (h0 < n_hyp) {
-        const int nh = (int64_t)n_hyp - h0 < kWave ? (int)((int64_t)n_hyp - h0) : kWave;
-        const uint32_t cnt = score_cluster(pts, sp, lane, s_hyp + wave * (kWave / 2), nh, tau);
-        // The lane's own hypothesis is re-read from LDS rather than kept in
-        // registers through the scoring loop.
-        const int64_t hl = h0 + lane;
-        if (lane < nh) {
-            if (hyp_counts != nullptr) hyp_counts[k * n_hyp + hl] = (int32_t)cnt;
-            if (!__builtin_isnan(reinterpret_cast<const float2 *>(s_hyp)[tid].x))
-                key = ((unsigned long long)cnt << 32) | (0xFFFFFFFFull - (uint32_t)hl);
-        }
-    }
-    key = wave_max_u64(key);
-    if (lane == 0) s_key[wave] = key;
-    __syncthreads();
-    if (tid == 0) {
-        for (int w = 1; w < kScoreBlock / kWave; ++w) key = s_key[w] > key ? s_key[w] : key;
-        if (key != 0) atomicMax(&best_key[k], key);
-    }
-}
-
-// One workgroup per cluster, clusters in the planned order: the kept
-// hypothesis (from best_key), FP64 re-classification of every point under it,
-// least-squares refit on its inliers (Sec. 3.2, Eq. 7, Alg. 2: normal equations
-// A^T A v = A^T v_d, summed per thread and reduced in a fixed tree) and heading
-// atan2(vy, vx) (Eq. 8).
-__global__ __launch_bounds__(kRefitBlock) void refit_kernel(
-    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_points,
-    uint32_t key0, uint32_t key1, Points pts, const unsigned long long *__restrict__ best_key,
-    float tau, Outputs o) {
-    __shared__ double s_sum[kRefitBlock / kWave][5];
-    __shared__ int s_cnt[kRefitBlock / kWave][2];
-    const int64_t k = order != nullptr ? order[blockIdx.x] : (int64_t)blockIdx.x;
+// Refit of one cluster by one workgroup of kRefitBlock threads: the kept
+// hypothesis (from its best key), FP64 re-classification of every point under
+// it, least-squares refit on its inliers (Sec. 3.2, Eq. 7, Alg. 2: normal
+// equations A^T A v = A^T v_d, summed per thread and reduced in a fixed tree)
+// and heading atan2(vy, vx) (Eq. 8).
+__device__ __forceinline__ void refit_block(Span sp, ClusterId id, unsigned long long best,
+                                            const Points &pts, float tau, const Outputs &o,
+                                            double (*s_sum)[5], int (*s_cnt)[2]) {
     const int tid = threadIdx.x;
     const int wave = tid / kWave;
     const int lane = tid % kWave;
-    const Span sp = cluster_span(off, k, n_points);
+    const int64_t k = id.out;
     if (!sp.ok || sp.n < 2) {
         if (tid == 0) write_failed(o, k, sp.ok ? RV_CLUSTER_TOO_FEW_POINTS : RV_CLUSTER_BAD_OFFSETS);
         return;
     }
-    const unsigned long long best = best_key[k];
     if (best == 0) {
         if (tid == 0) write_failed(o, k, RV_CLUSTER_ALL_DEGENERATE);
         return;
     }
     const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
-    const Hypothesis hy = make_hypothesis(pts, sp, hbest, (uint32_t)k, key0, key1);
+    const Hypothesis hy = make_hypothesis(pts, sp, hbest, id.local, id.key0, id.key1);
     const double dtau = tau;
 
     // Threads walk 64-aligned global blocks so one wave ballot maps onto two
@@ -514,6 +507,223 @@ __global__ __launch_bounds__(kRefitBlock) void refit_kernel(
     o.status[k] = RV_CLUSTER_OK;
 }
 
+// ---- single frame ---------------------------------------------------------
+
+// Work item = (cluster, block of 256 hypotheses).  Block i takes the item that
+// keeps clusters in the planned order while all items of one cluster run on the
+// same XCD (blocks are dealt to the 8 XCDs round-robin), sharing that XCD's L2
+// copy of the cluster's points.  Eight waves per SIMD: the scoring loop fits in
+// 64 VGPRs.
+__global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))) void score_kernel(
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
+    int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster, uint32_t key0, uint32_t key1,
+    Points pts, float tau, unsigned long long *__restrict__ best_key,
+    int32_t *__restrict__ hyp_counts) {
+    __shared__ float4 s_hyp[kScoreBlock / 2];  // (vx, vy) pairs, two per float4
+    __shared__ unsigned long long s_key[kScoreBlock / kWave];
+    const uint32_t xcd = blockIdx.x % kXcds;
+    const uint32_t r = blockIdx.x / kXcds;
+    const int64_t j = xcd + (int64_t)kXcds * (r / (uint32_t)blocks_per_cluster);
+    if (j >= n_clusters) return;
+    const int b = (int)(r % (uint32_t)blocks_per_cluster);
+    const int64_t k = order != nullptr ? order[j] : j;
+    ClusterId id;
+    id.out = k;
+    id.local = (uint32_t)k;
+    id.key0 = key0;
+    id.key1 = key1;
+    score_block(cluster_span(off, k, n_points), id, b, n_hyp, pts, tau, kRowsMax, s_hyp, s_key,
+                best_key, hyp_counts);
+}
+
+// One workgroup per cluster, clusters in the planned order.
+__global__ __launch_bounds__(kRefitBlock) void refit_kernel(
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_points,
+    uint32_t key0, uint32_t key1, Points pts, const unsigned long long *__restrict__ best_key,
+    float tau, Outputs o) {
+    __shared__ double s_sum[kRefitBlock / kWave][5];
+    __shared__ int s_cnt[kRefitBlock / kWave][2];
+    const int64_t k = order != nullptr ? order[blockIdx.x] : (int64_t)blockIdx.x;
+    ClusterId id;
+    id.out = k;
+    id.local = (uint32_t)k;
+    id.key0 = key0;
+    id.key1 = key1;
+    refit_block(cluster_span(off, k, n_points), id, best_key[k], pts, tau, o, s_sum, s_cnt);
+}
+
+// ---- many frames in one launch sequence ----------------------------------
+//
+// The frames share one CSR: frame f owns clusters [frame_off[f], frame_off[f+1]).
+// A cluster draws its hypotheses with its frame's seed and its index within
+// the frame, so its result is bitwise the one a single-frame call gives.  The
+// scoring kernel is persistent: a fixed grid drains a device work queue of
+// (cluster, 256-hypothesis block) items, clusters largest first.
+
+struct Batch {
+    const int32_t *frame_off;  // [n_frames + 1]
+    const uint64_t *seeds;     // [n_frames], device
+    int64_t n_frames;
+    int32_t *frame_of;         // [n_clusters], filled by batch_prep_kernel
+};
+
+// Register rows per pass for each cluster-size bucket: bucket 0 holds n < 64,
+// bucket b holds n in [32 * 2^b, 64 * 2^b), the last bucket everything larger.
+struct Tuning {
+    int32_t rows[RV_TUNE_BUCKETS];
+};
+
+__device__ __forceinline__ int size_bucket(int64_t n) {
+    int b = 0;
+    while (b < RV_TUNE_BUCKETS - 1 && n >= ((int64_t)64 << b)) ++b;
+    return b;
+}
+
+// Frame of cluster k: the last f with frame_off[f] <= k (binary search; stays
+// inside [0, n_frames) whatever the offsets hold).
+__device__ __forceinline__ int64_t frame_of_cluster(const int32_t *__restrict__ fo,
+                                                    int64_t n_frames, int64_t k) {
+    int64_t lo = 0, hi = n_frames;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (fo[mid] <= k)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ ClusterId batch_cluster(const Batch &bt, int64_t k) {
+    const int64_t f = bt.frame_of[k];
+    const uint64_t seed = bt.seeds[f];
+    ClusterId id;
+    id.out = k;
+    id.local = (uint32_t)(k - bt.frame_off[f]);
+    id.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    id.key1 = (uint32_t)(seed >> 32);
+    return id;
+}
+
+// Clears the size-class histogram and the work-queue head.
+__global__ __launch_bounds__(kSizeClasses) void batch_init_kernel(
+    uint32_t *__restrict__ hist, unsigned long long *__restrict__ queue_head) {
+    hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *queue_head = 0;
+}
+
+// One thread per point: staging as in prep_kernel.  One thread per cluster:
+// clear its best key, find its frame, count it in its size class (per-block
+// LDS histogram, one global atomic per class and block).
+__global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
+    float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
+    uint32_t *__restrict__ bits, int64_t n_words, const int32_t *__restrict__ off,
+    int64_t n_clusters, Batch bt, unsigned long long *__restrict__ best_key,
+    uint32_t *__restrict__ hist) {
+    __shared__ uint32_t local[kSizeClasses];
+    for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) local[c] = 0;
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
+    if (p < n_points) {
+        const float t = theta[p], v = vd[p];
+        double s, c;
+        sincos((double)t, &s, &c);
+        const bool ok = isfinite(t) && isfinite(v);
+        cs32[p] = make_float2(ok ? (float)c : 0.0f, ok ? (float)s : 0.0f);
+        v32[p] = ok ? v : __builtin_inff();
+        cs64[p] = make_double2(c, s);
+    }
+    if (bits != nullptr && p < n_words) bits[p] = 0u;
+    if (p < n_clusters) {
+        best_key[p] = 0;
+        bt.frame_of[p] = (int32_t)frame_of_cluster(bt.frame_off, bt.n_frames, p);
+        atomicAdd(&local[size_class(cluster_span(off, p, n_points).n)], 1u);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock)
+        if (local[c] != 0) atomicAdd(&hist[c], local[c]);
+}
+
+// Start of each size class in the dispatch order (largest class first).
+__global__ __launch_bounds__(64) void batch_scan_kernel(uint32_t *__restrict__ hist) {
+    if (threadIdx.x != 0) return;
+    uint32_t at = 0;
+    for (int c = kSizeClasses - 1; c >= 0; --c) {
+        const uint32_t n = hist[c];
+        hist[c] = at;
+        at += n;
+    }
+}
+
+// Places every cluster in the dispatch order: one global atomic per class and
+// block reserves a range, LDS atomics rank the block's clusters inside it.
+__global__ __launch_bounds__(kPrepBlock) void batch_scatter_kernel(
+    const int32_t *__restrict__ off, int64_t n_clusters, int64_t n_points,
+    uint32_t *__restrict__ start, int32_t *__restrict__ order) {
+    __shared__ uint32_t count[kSizeClasses];
+    __shared__ uint32_t base[kSizeClasses];
+    for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) count[c] = 0;
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
+    int cls = -1;
+    uint32_t rank = 0;
+    if (k < n_clusters) {
+        cls = size_class(cluster_span(off, k, n_points).n);
+        rank = atomicAdd(&count[cls], 1u);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock)
+        base[c] = count[c] != 0 ? atomicAdd(&start[c], count[c]) : 0u;
+    __syncthreads();
+    if (cls >= 0) order[base[cls] + rank] = (int32_t)k;
+}
+
+// Persistent scoring: each workgroup takes (cluster, block) items from the
+// queue until it is empty; every workgroup exits once the head passes the
+// last item.  The per-item tables (frame lookup, tuning) are copied to LDS
+// once, so they do not hold scalar registers through the scoring loop.  Seven
+// waves per SIMD keep the loop state out of spill code in the scoring passes.
+__global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))) void batch_score_kernel(
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
+    int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster, Batch bt, Points pts, float tau,
+    Tuning tune, unsigned long long *__restrict__ queue_head,
+    unsigned long long *__restrict__ best_key, int32_t *__restrict__ hyp_counts) {
+    __shared__ float4 s_hyp[kScoreBlock / 2];
+    __shared__ unsigned long long s_key[kScoreBlock / kWave];
+    __shared__ unsigned long long s_item;
+    __shared__ int32_t s_rows[RV_TUNE_BUCKETS];
+    __shared__ Batch s_bt;
+    if (threadIdx.x < RV_TUNE_BUCKETS) s_rows[threadIdx.x] = tune.rows[threadIdx.x];
+    if (threadIdx.x == 0) s_bt = bt;
+    const unsigned long long total = (unsigned long long)n_clusters * (unsigned long long)blocks_per_cluster;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(queue_head, 1ull);
+        __syncthreads();
+        const unsigned long long item = s_item;
+        __syncthreads();
+        if (item >= total) break;
+        const int64_t j = (int64_t)(item / (unsigned long long)blocks_per_cluster);
+        const int b = (int)(item % (unsigned long long)blocks_per_cluster);
+        const int64_t k = order[j];
+        const Span sp = cluster_span(off, k, n_points);
+        const Batch btl = s_bt;
+        const int rows = s_rows[size_bucket(sp.n)];
+        score_block(sp, batch_cluster(btl, k), b, n_hyp, pts, tau, rows, s_hyp, s_key, best_key,
+                    hyp_counts);
+    }
+}
+
+__global__ __launch_bounds__(kRefitBlock) void batch_refit_kernel(
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_points,
+    Batch bt, Points pts, const unsigned long long *__restrict__ best_key, float tau, Outputs o) {
+    __shared__ double s_sum[kRefitBlock / kWave][5];
+    __shared__ int s_cnt[kRefitBlock / kWave][2];
+    const int64_t k = order[blockIdx.x];
+    refit_block(cluster_span(off, k, n_points), batch_cluster(bt, k), best_key[k], pts, tau, o,
+                s_sum, s_cnt);
+}
+
 __global__ __launch_bounds__(kPrepBlock) void philox_kernel(const uint32_t *__restrict__ ctr,
                                                         const uint32_t *__restrict__ key,
                                                         uint32_t *__restrict__ out,
@@ -590,6 +800,186 @@ bool take_timed_call(TimedCall &tc) {
 void keep_timed_call(const TimedCall &tc) {
     std::lock_guard<std::mutex> lock(g_timing_mutex);
     g_pending.push_back(tc);
+}
+
+
+struct BatchLayout {
+    size_t cs32, v32, cs64, order, best_key, frame_of, hist, queue, total;
+};
+
+BatchLayout make_batch_layout(int64_t n_clusters, int64_t n_points) {
+    BatchLayout L;
+    const size_t np = (size_t)n_points, nc = (size_t)n_clusters;
+    size_t at = 0;
+    L.cs32 = at; at = align_up(at + np * sizeof(float2));
+    L.v32 = at; at = align_up(at + np * sizeof(float));
+    L.cs64 = at; at = align_up(at + np * sizeof(double2));
+    L.order = at; at = align_up(at + nc * sizeof(int32_t));
+    L.best_key = at; at = align_up(at + nc * sizeof(unsigned long long));
+    L.frame_of = at; at = align_up(at + nc * sizeof(int32_t));
+    L.hist = at; at = align_up(at + kSizeClasses * sizeof(uint32_t));
+    L.queue = at; at = align_up(at + sizeof(unsigned long long));
+    L.total = at;
+    return L;
+}
+
+struct BatchArgs {
+    const float *theta, *vd;
+    const int32_t *off, *frame_off;
+    const uint64_t *seeds;
+    int64_t n_frames, n_clusters, n_points;
+    int32_t n_hyp;
+    float tau;
+    Outputs o;
+    rv_tuning_t tuning;
+    void *workspace;
+    size_t workspace_bytes;
+};
+
+int check_batch(const BatchArgs &a) {
+    if (a.n_frames < 1 || a.n_frames > (int64_t)INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "n_frames must be in [1, 2^31 - 1]");
+    if (a.n_clusters < 0 || a.n_clusters > (int64_t)INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "n_clusters must be in [0, 2^31 - 1]");
+    if (a.n_points < 0 || a.n_points > INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "n_points must be in [0, 2^31 - 1]");
+    if (a.n_hyp < 1 || a.n_hyp > RV_MAX_HYP)
+        return fail(RV_ERR_INVALID_ARG, "n_hyp must be in [1, %d]", RV_MAX_HYP);
+    if (!(a.tau > 0.0f) || !isfinite(a.tau))
+        return fail(RV_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (a.off == nullptr || a.frame_off == nullptr || a.seeds == nullptr)
+        return fail(RV_ERR_INVALID_ARG, "cluster_offsets, frame_offsets or seeds is NULL");
+    if (a.n_points > 0 && (a.theta == nullptr || a.vd == nullptr))
+        return fail(RV_ERR_INVALID_ARG, "theta or vd is NULL");
+    if (a.n_clusters > 0 && (a.o.vx == nullptr || a.o.vy == nullptr || a.o.heading == nullptr ||
+                             a.o.n_inliers == nullptr || a.o.status == nullptr))
+        return fail(RV_ERR_INVALID_ARG, "a required output is NULL");
+    for (int b = 0; b < RV_TUNE_BUCKETS; ++b)
+        if (a.tuning.rows_max[b] < 1 || a.tuning.rows_max[b] > kRowsMax)
+            return fail(RV_ERR_INVALID_ARG, "tuning.rows_max must be in [1, %d]", kRowsMax);
+    if (a.tuning.blocks_per_cu < 0 || a.tuning.blocks_per_cu > 64)
+        return fail(RV_ERR_INVALID_ARG, "tuning.blocks_per_cu must be in [0, 64]");
+    const BatchLayout L = make_batch_layout(a.n_clusters, a.n_points);
+    if (a.workspace == nullptr || a.workspace_bytes < L.total)
+        return fail(RV_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                    a.workspace == nullptr ? (size_t)0 : a.workspace_bytes);
+    if (((uintptr_t)a.workspace % kAlign) != 0)
+        return fail(RV_ERR_WORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    return RV_OK;
+}
+
+int64_t batch_blocks_per_cluster(const BatchArgs &a) {
+    return ((int64_t)a.n_hyp + kScoreBlock - 1) / kScoreBlock;
+}
+
+// Persistent grid of the batched scoring kernel on the current device.
+int persistent_blocks(int blocks_per_cu, int64_t items, unsigned *grid) {
+    int dev = 0, cus = 0, fit = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_score_kernel, kScoreBlock, 0) !=
+            hipSuccess)
+        return fail(RV_ERR_HIP, "device query failed");
+    int per_cu = blocks_per_cu > 0 && blocks_per_cu < fit ? blocks_per_cu : fit;
+    if (per_cu < 1) per_cu = 1;
+    int64_t g = (int64_t)cus * per_cu;
+    if (g > items) g = items;
+    *grid = (unsigned)(g > 0 ? g : 1);
+    return RV_OK;
+}
+
+// The launch sequence of the batched form (argument checks and the persistent
+// grid size done by the caller, so that no device query falls inside a capture).
+int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_timing) {
+    if (a.n_clusters == 0) return RV_OK;
+    const BatchLayout L = make_batch_layout(a.n_clusters, a.n_points);
+    char *ws = (char *)a.workspace;
+    float2 *cs32 = (float2 *)(ws + L.cs32);
+    float *v32 = (float *)(ws + L.v32);
+    double2 *cs64 = (double2 *)(ws + L.cs64);
+    int32_t *order = (int32_t *)(ws + L.order);
+    unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
+    uint32_t *hist = (uint32_t *)(ws + L.hist);
+    unsigned long long *queue = (unsigned long long *)(ws + L.queue);
+    Points pts;
+    pts.cs32 = cs32;
+    pts.v32 = v32;
+    pts.cs64 = cs64;
+    pts.theta = a.theta;
+    Batch bt;
+    bt.frame_off = a.frame_off;
+    bt.seeds = a.seeds;
+    bt.n_frames = a.n_frames;
+    bt.frame_of = (int32_t *)(ws + L.frame_of);
+    Tuning tune;
+    for (int b = 0; b < RV_TUNE_BUCKETS; ++b) tune.rows[b] = a.tuning.rows_max[b];
+    const int64_t bpc = batch_blocks_per_cluster(a);
+    const int64_t n_words = a.o.bits != nullptr ? (a.n_points + 31) / 32 : 0;
+    int64_t prep_items = a.n_points > n_words ? a.n_points : n_words;
+    prep_items = prep_items > a.n_clusters ? prep_items : a.n_clusters;
+
+    TimedCall tc;
+    const bool timed = allow_timing && take_timed_call(tc);
+    if (timed) (void)hipEventRecord(tc.ev[0], st);
+    hipLaunchKernelGGL(batch_init_kernel, dim3(1), dim3(kSizeClasses), 0, st, hist, queue);
+    hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)((prep_items + kPrepBlock - 1) / kPrepBlock)),
+                       dim3(kPrepBlock), 0, st, a.theta, a.vd, a.n_points, cs32, v32, cs64,
+                       a.o.bits, n_words, a.off, a.n_clusters, bt, best_key, hist);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(64), 0, st, hist);
+    hipLaunchKernelGGL(batch_scatter_kernel,
+                       dim3((unsigned)((a.n_clusters + kPrepBlock - 1) / kPrepBlock)),
+                       dim3(kPrepBlock), 0, st, a.off, a.n_clusters, a.n_points, hist, order);
+    if (timed) (void)hipEventRecord(tc.ev[1], st);
+    hipLaunchKernelGGL(batch_score_kernel, dim3(grid), dim3(kScoreBlock), 0, st, a.off,
+                       (const int32_t *)order, a.n_clusters, a.n_points, a.n_hyp, (int32_t)bpc,
+                       bt, pts, a.tau, tune, queue, best_key, a.o.hyp_counts);
+    if (timed) (void)hipEventRecord(tc.ev[2], st);
+    hipLaunchKernelGGL(batch_refit_kernel, dim3((unsigned)a.n_clusters), dim3(kRefitBlock), 0, st,
+                       a.off, (const int32_t *)order, a.n_points, bt, pts,
+                       (const unsigned long long *)best_key, a.tau, a.o);
+    if (timed) {
+        (void)hipEventRecord(tc.ev[3], st);
+        keep_timed_call(tc);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(RV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return RV_OK;
+}
+
+BatchArgs make_batch_args(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                          const int32_t *frame_offsets, const uint64_t *seeds, int64_t n_frames,
+                          int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau,
+                          float *vx, float *vy, float *heading, int32_t *n_inliers,
+                          uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                          int32_t *hyp_counts, int32_t *best_hyp, const rv_tuning_t *tuning,
+                          void *workspace, size_t workspace_bytes) {
+    BatchArgs a;
+    a.theta = theta;
+    a.vd = vd;
+    a.off = cluster_offsets;
+    a.frame_off = frame_offsets;
+    a.seeds = seeds;
+    a.n_frames = n_frames;
+    a.n_clusters = n_clusters;
+    a.n_points = n_points;
+    a.n_hyp = n_hyp;
+    a.tau = tau;
+    a.o.vx = vx;
+    a.o.vy = vy;
+    a.o.heading = heading;
+    a.o.n_inliers = n_inliers;
+    a.o.status = status;
+    a.o.n_near = n_near_tau;
+    a.o.best = best_hyp;
+    a.o.hyp_counts = hyp_counts;
+    a.o.bits = inlier_bits;
+    if (tuning != nullptr)
+        a.tuning = *tuning;
+    else
+        rv_tuning_default(&a.tuning);
+    a.workspace = workspace;
+    a.workspace_bytes = workspace_bytes;
+    return a;
 }
 
 }  // namespace
@@ -740,6 +1130,105 @@ int rv_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out, in
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     return RV_OK;
+}
+
+
+void rv_tuning_default(rv_tuning_t *t) {
+    if (t == nullptr) return;
+    for (int b = 0; b < RV_TUNE_BUCKETS; ++b) t->rows_max[b] = kRowsMax;
+    t->blocks_per_cu = 0;
+}
+
+size_t rv_batch_workspace_bytes(int64_t n_frames, int64_t n_clusters, int64_t n_points,
+                                int32_t n_hyp) {
+    if (n_frames < 1 || n_clusters < 0 || n_points < 0 || n_hyp < 0) return 0;
+    return make_batch_layout(n_clusters, n_points).total;
+}
+
+int rv_estimate_velocity_batch(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                               const int32_t *frame_offsets, const uint64_t *seeds,
+                               int64_t n_frames, int64_t n_clusters, int64_t n_points,
+                               int32_t n_hyp, float tau, float *vx, float *vy, float *heading,
+                               int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
+                               uint32_t *inlier_bits, int32_t *hyp_counts, int32_t *best_hyp,
+                               const rv_tuning_t *tuning, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+    g_error[0] = '\0';
+    const BatchArgs a = make_batch_args(theta, vd, cluster_offsets, frame_offsets, seeds,
+                                        n_frames, n_clusters, n_points, n_hyp, tau, vx, vy,
+                                        heading, n_inliers, status, n_near_tau, inlier_bits,
+                                        hyp_counts, best_hyp, tuning, workspace, workspace_bytes);
+    if (int rc = check_batch(a)) return rc;
+    unsigned grid = 1;
+    if (a.n_clusters > 0)
+        if (int rc = persistent_blocks(a.tuning.blocks_per_cu, a.n_clusters * batch_blocks_per_cluster(a), &grid))
+            return rc;
+    return launch_batch(a, grid, (hipStream_t)stream, true);
+}
+
+struct rv_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int rv_graph_capture_batch(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                           const int32_t *frame_offsets, const uint64_t *seeds, int64_t n_frames,
+                           int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau,
+                           float *vx, float *vy, float *heading, int32_t *n_inliers,
+                           uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                           int32_t *hyp_counts, int32_t *best_hyp, const rv_tuning_t *tuning,
+                           void *workspace, size_t workspace_bytes, rv_graph_t **graph) {
+    g_error[0] = '\0';
+    if (graph == nullptr) return fail(RV_ERR_INVALID_ARG, "graph is NULL");
+    *graph = nullptr;
+    const BatchArgs a = make_batch_args(theta, vd, cluster_offsets, frame_offsets, seeds,
+                                        n_frames, n_clusters, n_points, n_hyp, tau, vx, vy,
+                                        heading, n_inliers, status, n_near_tau, inlier_bits,
+                                        hyp_counts, best_hyp, tuning, workspace, workspace_bytes);
+    if (int rc = check_batch(a)) return rc;
+    unsigned grid = 1;
+    if (a.n_clusters > 0)
+        if (int rc = persistent_blocks(a.tuning.blocks_per_cu, a.n_clusters * batch_blocks_per_cluster(a), &grid))
+            return rc;
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return fail(RV_ERR_HIP, "hipStreamCreate failed");
+    rv_graph_t *g = new rv_graph_t;
+    g->graph = nullptr;
+    g->exec = nullptr;
+    int rc = RV_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = fail(RV_ERR_HIP, "hipStreamBeginCapture failed");
+    } else {
+        rc = launch_batch(a, grid, cap, false);
+        const hipError_t e = hipStreamEndCapture(cap, &g->graph);
+        if (rc == RV_OK && e != hipSuccess)
+            rc = fail(RV_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        if (rc == RV_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+            rc = fail(RV_ERR_HIP, "hipGraphInstantiate failed");
+    }
+    (void)hipStreamDestroy(cap);
+    if (rc != RV_OK) {
+        rv_graph_destroy(g);
+        return rc;
+    }
+    *graph = g;
+    return RV_OK;
+}
+
+int rv_graph_launch(rv_graph_t *graph, void *stream) {
+    g_error[0] = '\0';
+    if (graph == nullptr || graph->exec == nullptr) return fail(RV_ERR_INVALID_ARG, "graph is NULL");
+    const hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(RV_ERR_HIP, "hipGraphLaunch failed: %s", hipGetErrorString(e));
+    return RV_OK;
+}
+
+void rv_graph_destroy(rv_graph_t *graph) {
+    if (graph == nullptr) return;
+    if (graph->exec != nullptr) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph != nullptr) (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 }  // extern "C"

@@ -86,7 +86,27 @@ WORKLOADS = {
 }
 # Data seed of each workload and the per-frame hypothesis seed convention:
 # hypothesis seed = (workload number << 32) | frame index.
-WORKLOAD_NUMBER = {"small": 1, "dense": 2}
+WORKLOAD_NUMBER = {"small": 1, "dense": 2, "batched": 3, "served": 4}
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchSpec:
+    """Many frames: cluster counts uniform in [clusters_lo, clusters_hi] per frame."""
+
+    n_frames: int
+    clusters_lo: int
+    clusters_hi: int
+    frame: FrameSpec          # its n_clusters is replaced per frame
+
+
+# "batched": 256 frames of U{100..1500} clusters, log-uniform [8, 2048] points,
+#            20 % uniform outliers, 512 hypotheses.
+# "served":  frames of U{200..1200} clusters, log-uniform [8, 1024] points, 25 %
+#            uniform outliers, 512 hypotheses (the frames of the request loop).
+BATCH_WORKLOADS = {
+    "batched": (BatchSpec(256, 100, 1500, FrameSpec(0, "loguniform", 8, 2048, p_uniform=0.20)), 512, 0.15),
+    "served": (BatchSpec(64, 200, 1200, FrameSpec(0, "loguniform", 8, 1024, p_uniform=0.25)), 512, 0.15),
+}
 
 
 def ransac_seed(workload: str, frame_index: int = 0) -> int:
@@ -187,3 +207,48 @@ def evals_per_frame(offsets: np.ndarray, n_hyp: int) -> int:
     """Nominal hypothesis-point evaluations: sum of n_hyp * n_i over clusters with n_i >= 2."""
     sizes = np.diff(np.asarray(offsets, dtype=np.int64))
     return int(n_hyp * sizes[sizes >= 2].sum())
+
+
+@dataclasses.dataclass
+class Batch:
+    """Frames concatenated into one CSR, with each frame's cluster range and seed."""
+
+    frame: Frame                 # all frames' clusters, in frame order
+    frame_offsets: np.ndarray    # int32 [F+1]: frame f owns clusters [fo[f], fo[f+1])
+    seeds: np.ndarray            # uint64 [F]: hypothesis seed of each frame
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.frame_offsets.shape[0] - 1)
+
+    def frame_slice(self, f: int) -> Frame:
+        """Frame f alone (its clusters re-based to start at point 0)."""
+        c0, c1 = int(self.frame_offsets[f]), int(self.frame_offsets[f + 1])
+        p0, p1 = int(self.frame.offsets[c0]), int(self.frame.offsets[c1])
+        return Frame(theta=self.frame.theta[p0:p1], vd=self.frame.vd[p0:p1],
+                     offsets=(self.frame.offsets[c0:c1 + 1] - p0).astype(np.int32),
+                     truth_vx=self.frame.truth_vx[c0:c1], truth_vy=self.frame.truth_vy[c0:c1],
+                     kind=self.frame.kind[p0:p1])
+
+
+def frame_seed(workload: str, frame_index: int) -> int:
+    return ransac_seed(workload, frame_index)
+
+
+def make_batch(spec: BatchSpec, seed: int, workload: str = "batched", n_frames: int | None = None) -> Batch:
+    """Frames f = 0..F-1: cluster count drawn from PCG64(seed), frame data from
+    make_frame with data seed (seed << 20) + f, hypothesis seed frame_seed(workload, f)."""
+    F = spec.n_frames if n_frames is None else n_frames
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = rng.integers(spec.clusters_lo, spec.clusters_hi + 1, size=F)
+    frames = [make_frame(dataclasses.replace(spec.frame, n_clusters=int(c)), (seed << 20) + f)
+              for f, c in enumerate(counts)]
+    fo = np.zeros(F + 1, dtype=np.int64)
+    np.cumsum(counts, out=fo[1:])
+    seeds = np.array([frame_seed(workload, f) for f in range(F)], dtype=np.uint64)
+    return Batch(frame=concat_frames(frames), frame_offsets=fo.astype(np.int32), seeds=seeds)
+
+
+def make_batch_workload(name: str, n_frames: int | None = None) -> tuple[Batch, int, float]:
+    spec, n_hyp, tau = BATCH_WORKLOADS[name]
+    return make_batch(spec, WORKLOAD_NUMBER[name], workload=name, n_frames=n_frames), n_hyp, tau

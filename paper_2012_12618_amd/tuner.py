@@ -1,0 +1,137 @@
+"""Autotuner for the batched form.
+
+Two launch parameters of ``rv_estimate_velocity_batch`` change only its speed,
+never a result bit:
+
+* ``rows_max[b]``: register rows of 64 points a wave holds per pass over a
+  cluster of size bucket b (bucket 0: n < 64; bucket b >= 1: 32*2^b <= n <
+  64*2^b; the last bucket: everything larger).  More rows mean fewer passes,
+  so fewer re-reads of the hypotheses from LDS; fewer rows mean less work
+  wasted in the last, partial pass of a cluster.
+* ``blocks_per_cu``: workgroups of the persistent scoring grid per compute
+  unit (0: as many as fit).
+
+Hypotheses per wave are fixed at 64 (one per lane, which is where the wave's
+inlier count of each hypothesis lands), so the tile the tuner picks is the
+point tile.
+
+The tuner times whole batched calls on the caller's own inputs (coordinate
+descent: one bucket at a time, then the grid), keeps the fastest setting per
+coordinate, and can save the table as JSON keyed by device name and n_hyp.
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+
+import torch
+
+from . import binding
+
+ROW_CANDIDATES = (4, 8, 12, 16)
+GRID_CANDIDATES = (0, 1, 2, 4)
+
+
+def size_bucket(n: int) -> int:
+    """Bucket of a cluster of n points (the kernel's own rule)."""
+    b = 0
+    while b < binding.RV_TUNE_BUCKETS - 1 and n >= (64 << b):
+        b += 1
+    return b
+
+
+def buckets_in_use(offsets_host) -> list[int]:
+    """Buckets where rows_max can matter: clusters longer than the smallest candidate tile."""
+    import numpy as np
+
+    sizes = np.diff(np.asarray(offsets_host, dtype=np.int64))
+    used = set()
+    for n in np.unique(sizes):
+        if n > 64 * min(ROW_CANDIDATES):
+            used.add(size_bucket(int(n)))
+    return sorted(used)
+
+
+def _time_call(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+def autotune(theta, vd, offsets, frame_offsets, seeds, n_hyp: int, tau: float, *,
+             offsets_host=None, reps: int = 3, rows=ROW_CANDIDATES, grids=GRID_CANDIDATES,
+             log=None) -> tuple[binding.RVTuning, dict]:
+    """Pick rows_max per bucket and blocks_per_cu for this batch; returns (tuning, report)."""
+    n_frames = int(frame_offsets.numel()) - 1
+    out = binding.allocate_batch_outputs(n_frames, int(offsets.numel()) - 1, int(theta.numel()),
+                                         n_hyp, theta.device)
+    if offsets_host is None:
+        offsets_host = offsets.cpu().numpy()
+    best = binding.rv_tuning_default()
+
+    def run(t):
+        binding.rv_estimate_velocity_batch(theta, vd, offsets, frame_offsets, seeds, n_hyp, tau,
+                                           tuning=t, out=out)
+
+    best_ms = _time_call(lambda: run(best), reps)
+    trials = [{"tuning": best.to_dict(), "ms": best_ms}]
+    for b in buckets_in_use(offsets_host):
+        for r in rows:
+            if r == best.rows_max[b]:
+                continue
+            cand = binding.RVTuning.from_dict(best.to_dict())
+            cand.rows_max[b] = r
+            ms = _time_call(lambda: run(cand), reps)
+            trials.append({"tuning": cand.to_dict(), "ms": ms})
+            if log:
+                log(f"bucket {b} rows {r}: {ms:.3f} ms (best {best_ms:.3f})")
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    for gsz in grids:
+        if gsz == best.blocks_per_cu:
+            continue
+        cand = binding.RVTuning.from_dict(best.to_dict())
+        cand.blocks_per_cu = gsz
+        ms = _time_call(lambda: run(cand), reps)
+        trials.append({"tuning": cand.to_dict(), "ms": ms})
+        if log:
+            log(f"blocks_per_cu {gsz}: {ms:.3f} ms (best {best_ms:.3f})")
+        if ms < best_ms:
+            best, best_ms = cand, ms
+    return best, {"best": best.to_dict(), "best_ms": best_ms, "trials": trials}
+
+
+def table_key(device_name: str, n_hyp: int) -> str:
+    return f"{device_name}|H={int(n_hyp)}"
+
+
+def save(path: str, device_name: str, n_hyp: int, tuning: binding.RVTuning) -> None:
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    table[table_key(device_name, n_hyp)] = tuning.to_dict()
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load(path: str, device_name: str, n_hyp: int) -> binding.RVTuning | None:
+    """The saved tuning for this device and n_hyp, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    d = table.get(table_key(device_name, n_hyp))
+    return None if d is None else binding.RVTuning.from_dict(d)

@@ -117,3 +117,46 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         binding.load_library()
+
+
+def test_batch_host_argument_checks(lib):
+    from paper_2012_12618_amd import binding
+
+    fake = ctypes.c_void_p(4096)
+    t = binding.rv_tuning_default()
+    assert list(t.rows_max) == [16] * binding.RV_TUNE_BUCKETS and t.blocks_per_cu == 0
+    assert binding.rv_batch_workspace_bytes(0, 10, 10, 8) == 0
+    a = binding.rv_batch_workspace_bytes(4, 100, 10000, 512)
+    b = binding.rv_batch_workspace_bytes(4, 100, 20000, 512)
+    assert 0 < a < b
+
+    def call(**kw):
+        args = dict(theta=fake, vd=fake, off=fake, fo=fake, seeds=fake, F=2, K=10, N=100, H=64,
+                    tau=0.15, out=fake, tuning=None, ws=None, ws_bytes=0)
+        args.update(kw)
+        tune = args["tuning"]
+        return lib.rv_estimate_velocity_batch(
+            args["theta"], args["vd"], args["off"], args["fo"], args["seeds"], args["F"], args["K"],
+            args["N"], args["H"], args["tau"], args["out"], args["out"], args["out"], args["out"],
+            args["out"], None, None, None, None, None if tune is None else ctypes.byref(tune),
+            args["ws"], args["ws_bytes"], None)
+
+    cases = [
+        (dict(F=0), -1, "n_frames"),
+        (dict(seeds=None), -1, "seeds"),
+        (dict(fo=None), -1, "frame_offsets"),
+        (dict(H=0), -1, "n_hyp"),
+        (dict(tau=-1.0), -1, "tau"),
+        (dict(out=None), -1, "output"),
+        (dict(), -2, "workspace"),
+    ]
+    for kw, code, word in cases:
+        assert call(**kw) == code, kw
+        assert word in lib.rv_last_error().decode()
+    bad = binding.RVTuning.from_dict({"rows_max": [17] * 8, "blocks_per_cu": 0})
+    assert call(tuning=bad, ws=fake, ws_bytes=1 << 30) == -1
+    assert "rows_max" in lib.rv_last_error().decode()
+    # nothing to do
+    assert call(K=0, N=0, ws=fake, ws_bytes=1 << 20) == 0
+    assert lib.rv_graph_launch(None, None) == -1
+    lib.rv_graph_destroy(None)
