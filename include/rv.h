@@ -40,7 +40,8 @@ typedef enum {
     RV_OK = 0,
     RV_ERR_INVALID_ARG = -1, /* null pointer, bad size or scalar */
     RV_ERR_WORKSPACE = -2,   /* workspace missing or smaller than rv_workspace_bytes() */
-    RV_ERR_HIP = -3          /* a HIP launch failed; rv_last_error() has the HIP message */
+    RV_ERR_HIP = -3,         /* a HIP launch failed; rv_last_error() has the HIP message */
+    RV_ERR_BUSY = -4         /* server: its queue of waiting frames is full, submit again later */
 } rv_status_t;
 
 /* Per-cluster status byte. */
@@ -178,6 +179,101 @@ int rv_graph_capture_batch(const float *theta, const float *vd, const int32_t *c
                            void *workspace, size_t workspace_bytes, rv_graph_t **graph);
 int rv_graph_launch(rv_graph_t *graph, void *stream);
 void rv_graph_destroy(rv_graph_t *graph);
+
+/*
+ * Frame server (request loop with continuous batching).
+ *
+ * A server owns one device arena of hbm_budget_bytes (allocated once, at
+ * creation), a pool of pinned host buffers, n_streams launch slots and two
+ * threads.  rv_server_submit copies a frame from caller HOST memory into a
+ * pinned buffer and queues it.  The scheduler thread admits waiting frames in
+ * arrival order whenever a launch slot is free: as many as fit, together, in
+ * the arena's largest free range (inputs, workspace and outputs of the batch)
+ * and in max_batch_frames; it copies them to the device and launches them as
+ * one rv_estimate_velocity_batch call on the slot's stream, followed by one
+ * copy of the per-cluster results to pinned host memory.  Frames that arrive
+ * while batches are on the GPU go into the next free slot, so their copies and
+ * kernels overlap the running ones.  The completion thread waits for each
+ * batch, hands the results to its frames and frees the batch's arena range.
+ *
+ * Each frame's results are those of rv_estimate_velocity on that frame alone
+ * with its seed, whatever else is in flight (bitwise: the batched path draws a
+ * cluster's hypotheses from its frame's seed and its index within the frame).
+ *
+ * Threading: submit, wait, result and stats may be called from any threads.
+ * Tickets are unique per server; a ticket's results are held until
+ * rv_server_result takes them.
+ */
+typedef struct rv_server rv_server_t;
+
+typedef struct {
+    int32_t n_hyp;               /* hypotheses per cluster, [1, RV_MAX_HYP] */
+    float tau;                   /* inlier threshold, m/s, finite and > 0 */
+    size_t hbm_budget_bytes;     /* device arena size, >= 1 MiB */
+    int32_t max_batch_frames;    /* frames per launch, >= 1 */
+    int32_t n_streams;           /* launch slots in flight, [1, 8] */
+    int32_t max_waiting_frames;  /* submitted, not yet launched frames before RV_ERR_BUSY, >= 1 */
+    rv_tuning_t tuning;
+} rv_server_config_t;
+
+/* Defaults: n_hyp 512, tau 0.15, 16 GiB, 64 frames per launch, 2 slots,
+   1024 waiting frames, default tuning. */
+void rv_server_config_default(rv_server_config_t *cfg);
+
+/* Device memory that one frame of n_clusters clusters and n_points points
+   takes in the arena when it is launched alone (0 for invalid sizes). */
+size_t rv_server_frame_bytes(const rv_server_config_t *cfg, int64_t n_clusters,
+                             int64_t n_points);
+
+/* Creates a server on the current device.  RV_OK, RV_ERR_INVALID_ARG or
+   RV_ERR_HIP (arena, pinned memory, streams or threads could not be made). */
+int rv_server_create(const rv_server_config_t *cfg, rv_server_t **server);
+
+/*
+ * Queues one frame.  theta[n_points], vd[n_points], cluster_offsets[n_clusters
+ * + 1] are HOST arrays, copied before the call returns.  Offsets must satisfy
+ * 0 <= offsets[k] <= offsets[k+1] <= n_points.  *ticket receives the frame's
+ * ticket.  RV_ERR_INVALID_ARG for bad arguments or a frame larger than the
+ * whole arena, RV_ERR_BUSY when max_waiting_frames frames are waiting.
+ */
+int rv_server_submit(rv_server_t *server, const float *theta, const float *vd,
+                     const int32_t *cluster_offsets, int64_t n_clusters, int64_t n_points,
+                     uint64_t seed, uint64_t *ticket);
+
+/* Waits up to timeout_ms (negative: no limit) for a ticket's results: 1 ready,
+   0 not yet, RV_ERR_INVALID_ARG for an unknown ticket, RV_ERR_HIP if its batch
+   failed. */
+int rv_server_wait(rv_server_t *server, uint64_t ticket, int64_t timeout_ms);
+
+/* Host-clock times of one frame, nanoseconds since the server's creation. */
+typedef struct {
+    int64_t submitted_ns;   /* rv_server_submit copied it */
+    int64_t launched_ns;    /* its batch was enqueued */
+    int64_t done_ns;        /* its batch's results were in host memory */
+    int32_t batch_frames;   /* frames in its batch */
+    int32_t slot;           /* launch slot of its batch */
+} rv_frame_times_t;
+
+/* Copies a ready ticket's per-cluster results into HOST arrays of its
+   n_clusters entries (n_near_tau and times nullable) and forgets the ticket.
+   RV_OK, RV_ERR_INVALID_ARG (unknown ticket, NULL output) or RV_ERR_BUSY (not
+   ready yet). */
+int rv_server_result(rv_server_t *server, uint64_t ticket, float *vx, float *vy, float *heading,
+                     int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
+                     rv_frame_times_t *times);
+
+typedef struct {
+    int64_t frames_submitted, frames_done, batches, busy_rejections;
+    int64_t max_batch_frames_seen;
+    int64_t arena_bytes, arena_peak_bytes;  /* budget and the most of it ever in use */
+    int64_t pinned_bytes;                   /* pinned host memory held by the pool */
+    int64_t waiting_frames, inflight_batches;
+} rv_server_stats_t;
+int rv_server_stats(rv_server_t *server, rv_server_stats_t *stats);
+
+/* Finishes every submitted frame, stops the threads and frees everything;
+   results not taken are dropped. */
+void rv_server_destroy(rv_server_t *server);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *rv_last_error(void);

@@ -15,6 +15,7 @@ _BINDING_NAMES = (
     "rv_stage_times", "rv_philox4x32_10", "allocate_outputs", "load_library", "RVError",
     "rv_tuning_default", "rv_batch_workspace_bytes", "rv_estimate_velocity_batch",
     "rv_graph_capture_batch", "allocate_batch_outputs", "RVTuning", "RVGraph",
+    "RVServer", "RVServerConfig", "rv_server_config_default", "rv_server_frame_bytes",
 )
 
 __all__ = list(_BINDING_NAMES)

@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -18,6 +19,7 @@ RV_OK = 0
 RV_ERR_INVALID_ARG = -1
 RV_ERR_WORKSPACE = -2
 RV_ERR_HIP = -3
+RV_ERR_BUSY = -4
 
 RV_CLUSTER_OK = 0
 RV_CLUSTER_TOO_FEW_POINTS = 1
@@ -53,6 +55,34 @@ class RVTuning(ctypes.Structure):
             t.rows_max[i] = int(r)
         t.blocks_per_cu = int(d.get("blocks_per_cu", 0))
         return t
+
+
+class RVServerConfig(ctypes.Structure):
+    """rv_server_config_t."""
+
+    _fields_ = [("n_hyp", ctypes.c_int32), ("tau", ctypes.c_float),
+                ("hbm_budget_bytes", ctypes.c_size_t), ("max_batch_frames", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("max_waiting_frames", ctypes.c_int32),
+                ("tuning", RVTuning)]
+
+
+class RVFrameTimes(ctypes.Structure):
+    """rv_frame_times_t: host-clock ns since the server's creation."""
+
+    _fields_ = [("submitted_ns", ctypes.c_int64), ("launched_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("batch_frames", ctypes.c_int32),
+                ("slot", ctypes.c_int32)]
+
+
+class RVServerStats(ctypes.Structure):
+    """rv_server_stats_t."""
+
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "frames_submitted", "frames_done", "batches", "busy_rejections", "max_batch_frames_seen",
+        "arena_bytes", "arena_peak_bytes", "pinned_bytes", "waiting_frames", "inflight_batches")]
+
+    def to_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 class RVError(RuntimeError):
@@ -102,6 +132,22 @@ def load_library() -> ctypes.CDLL:
     lib.rv_graph_launch.argtypes = [P, P]
     lib.rv_graph_destroy.restype = None
     lib.rv_graph_destroy.argtypes = [P]
+    lib.rv_server_config_default.restype = None
+    lib.rv_server_config_default.argtypes = [P]
+    lib.rv_server_frame_bytes.restype = ctypes.c_size_t
+    lib.rv_server_frame_bytes.argtypes = [P, i64, i64]
+    lib.rv_server_create.restype = ctypes.c_int
+    lib.rv_server_create.argtypes = [P, P]
+    lib.rv_server_submit.restype = ctypes.c_int
+    lib.rv_server_submit.argtypes = [P, P, P, P, i64, i64, ctypes.c_uint64, P]
+    lib.rv_server_wait.restype = ctypes.c_int
+    lib.rv_server_wait.argtypes = [P, ctypes.c_uint64, i64]
+    lib.rv_server_result.restype = ctypes.c_int
+    lib.rv_server_result.argtypes = [P, ctypes.c_uint64, P, P, P, P, P, P, P]
+    lib.rv_server_stats.restype = ctypes.c_int
+    lib.rv_server_stats.argtypes = [P, P]
+    lib.rv_server_destroy.restype = None
+    lib.rv_server_destroy.argtypes = [P]
     _lib = lib
     return lib
 
@@ -363,3 +409,95 @@ def rv_graph_capture_batch(theta, vd, offsets, frame_offsets, seeds, n_hyp: int,
     handle = ctypes.c_void_p()
     _check(lib.rv_graph_capture_batch(*args, ctypes.byref(handle)))
     return RVGraph(handle, (theta, vd, offsets, frame_offsets, seeds, out, tune))
+
+
+# ---- frame server -----------------------------------------------------------
+
+def rv_server_config_default() -> RVServerConfig:
+    c = RVServerConfig()
+    load_library().rv_server_config_default(ctypes.byref(c))
+    return c
+
+
+def rv_server_frame_bytes(cfg: RVServerConfig, n_clusters: int, n_points: int) -> int:
+    return int(load_library().rv_server_frame_bytes(ctypes.byref(cfg), int(n_clusters), int(n_points)))
+
+
+class RVServer:
+    """rv_server_t: frames in host memory in, per-cluster results in host memory out.
+
+    Submit copies the frame before returning; ``result`` returns numpy arrays.
+    The arena and the threads live until ``destroy`` (or garbage collection).
+    """
+
+    def __init__(self, cfg: RVServerConfig | None = None, **overrides):
+        lib = load_library()
+        self.cfg = cfg if cfg is not None else rv_server_config_default()
+        for k, v in overrides.items():
+            if k == "tuning":
+                self.cfg.tuning = v
+            else:
+                setattr(self.cfg, k, v)
+        handle = ctypes.c_void_p()
+        _check(lib.rv_server_create(ctypes.byref(self.cfg), ctypes.byref(handle)))
+        self._h = handle
+        self._sizes: dict[int, int] = {}
+
+    def submit(self, theta: np.ndarray, vd: np.ndarray, offsets: np.ndarray, seed: int) -> int:
+        """Queue one frame; returns its ticket.  Raises RVError (code RV_ERR_BUSY when full)."""
+        theta = np.ascontiguousarray(theta, np.float32)
+        vd = np.ascontiguousarray(vd, np.float32)
+        offsets = np.ascontiguousarray(offsets, np.int32)
+        n_points, n_clusters = int(theta.shape[0]), int(offsets.shape[0]) - 1
+        if vd.shape[0] != n_points or n_clusters < 0:
+            raise ValueError("theta and vd must have the same length; offsets needs >= 1 entry")
+        t = ctypes.c_uint64()
+        _check(load_library().rv_server_submit(
+            self._h, theta.ctypes.data_as(ctypes.c_void_p), vd.ctypes.data_as(ctypes.c_void_p),
+            offsets.ctypes.data_as(ctypes.c_void_p), n_clusters, n_points,
+            int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(t)))
+        self._sizes[int(t.value)] = n_clusters
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
+        rc = load_library().rv_server_wait(self._h, int(ticket), int(timeout_ms))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
+
+    def result(self, ticket: int) -> dict:
+        """Per-cluster results of a finished ticket (waits for it first)."""
+        self.wait(ticket)
+        K = self._sizes.pop(int(ticket))
+        out = {"vx": np.empty(K, np.float32), "vy": np.empty(K, np.float32),
+               "heading": np.empty(K, np.float32), "n_inliers": np.empty(K, np.int32),
+               "status": np.empty(K, np.uint8), "n_near_tau": np.empty(K, np.int32)}
+        times = RVFrameTimes()
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        _check(load_library().rv_server_result(
+            self._h, int(ticket), ptr(out["vx"]), ptr(out["vy"]), ptr(out["heading"]),
+            ptr(out["n_inliers"]), ptr(out["status"]), ptr(out["n_near_tau"]), ctypes.byref(times)))
+        out["times"] = {n: int(getattr(times, n)) for n, _ in RVFrameTimes._fields_}
+        return out
+
+    def stats(self) -> dict:
+        st = RVServerStats()
+        _check(load_library().rv_server_stats(self._h, ctypes.byref(st)))
+        return st.to_dict()
+
+    def destroy(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().rv_server_destroy(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,4 +1,5 @@
-"""Build the gfx950 shared library ``_lib/librv.so`` from ``csrc/rv.hip``.
+"""Build the gfx950 shared library ``_lib/librv.so`` from ``csrc/rv.hip`` (kernels
+and estimator entry points) and ``csrc/rv_server.cpp`` (frame server).
 
 Usage: ``python -m paper_2012_12618_amd.build`` (also called by the repository's
 ``__graft_entry__.build()``).  hipcc cross-compiles for gfx950 without a GPU.
@@ -12,7 +13,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "rv.hip")
+SRCS = [os.path.join(HERE, "csrc", "rv.hip"), os.path.join(HERE, "csrc", "rv_server.cpp")]
 INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "librv.so")
@@ -37,7 +38,7 @@ def hipcc_path() -> str:
 def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
     os.makedirs(LIB_DIR, exist_ok=True)
     tmp = LIB + ".tmp"
-    cmd = [hipcc_path(), *HIP_FLAGS, *(extra_flags or []), "-I", INCLUDE, "-o", tmp, SRC]
+    cmd = [hipcc_path(), *HIP_FLAGS, *(extra_flags or []), "-I", INCLUDE, "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -36,10 +36,24 @@
 #include <vector>
 
 #include "rv.h"
+#include "rv_internal.h"
 
 // v_writelane_b32: write a wave-uniform value into one lane of a VGPR (the
 // LLVM intrinsic; clang exposes no builtin for it).
 __device__ int amdgcn_writelane(int value, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// Error text shared by every translation unit of the library.
+namespace rv_internal {
+thread_local char g_error[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_error, sizeof g_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+}  // namespace rv_internal
 
 namespace {
 
@@ -143,6 +157,13 @@ __device__ __forceinline__ Hypothesis make_hypothesis(const Points &pts, Span sp
     hy.vx = (dvi * sj - dvj * si) * inv_det;
     hy.vy = (ci * dvj - cj * dvi) * inv_det;
     return hy;
+}
+
+// Lane 0's value of v in every lane, as a wave-uniform (scalar) value.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
@@ -368,9 +389,9 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
     key = wave_max_u64(key);
     if (lane == 0) s_key[wave] = key;
     __syncthreads();
-    if (tid == 0) {
+    if (wave == 0) {  // wave-uniform guard; one lane merges the block's key
         for (int w = 1; w < kScoreBlock / kWave; ++w) key = s_key[w] > key ? s_key[w] : key;
-        if (key != 0) atomicMax(&best_key[id.out], key);
+        if (lane == 0 && key != 0) atomicMax(&best_key[id.out], key);
     }
 }
 
@@ -697,10 +718,21 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))
     if (threadIdx.x < RV_TUNE_BUCKETS) s_rows[threadIdx.x] = tune.rows[threadIdx.x];
     if (threadIdx.x == 0) s_bt = bt;
     const unsigned long long total = (unsigned long long)n_clusters * (unsigned long long)blocks_per_cluster;
+    // Every branch that leads to or around a barrier in this loop is taken on a
+    // wave-uniform value (wave index, item read back with readfirstlane).  With
+    // a per-lane guard such as threadIdx.x == 0 the compiler may thread that
+    // guard across the loop's back edge into a lane-masked inner loop that lane
+    // 0 leaves to fetch the next item while lanes 1..63 wait on the old one.
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lane = threadIdx.x % kWave;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(queue_head, 1ull);
+        if (wave == 0) {
+            unsigned long long got = 0;
+            if (lane == 0) got = atomicAdd(queue_head, 1ull);
+            s_item = uniform_u64(got);  // the same value from every lane of wave 0
+        }
         __syncthreads();
-        const unsigned long long item = s_item;
+        const unsigned long long item = uniform_u64(s_item);
         __syncthreads();
         if (item >= total) break;
         const int64_t j = (int64_t)(item / (unsigned long long)blocks_per_cluster);
@@ -743,15 +775,8 @@ __global__ __launch_bounds__(kPrepBlock) void philox_kernel(const uint32_t *__re
 // Host side
 // ---------------------------------------------------------------------------
 
-thread_local char g_error[512] = "";
-
-int fail(int code, const char *fmt, ...) {
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_error, sizeof g_error, fmt, ap);
-    va_end(ap);
-    return code;
-}
+using rv_internal::fail;
+using rv_internal::g_error;
 
 constexpr size_t kAlign = 256;
 

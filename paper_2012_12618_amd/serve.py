@@ -1,0 +1,158 @@
+"""Served form: simulated radars sending frames to the frame server.
+
+``RVServer`` (the C server of include/rv.h) does the serving: the request
+queue, admission by the device-memory budget, continuous batching over launch
+slots and the copies.  This module only drives it the way a deployment would:
+``arrival_schedule`` draws when each radar's frames arrive, ``run_traffic``
+submits them at those times from one thread while another collects results,
+and the report gives p50/p99 frame latency and throughput.
+
+Arrivals: every radar sends frames as a Poisson process of rate ``fps``
+(exponential gaps with mean 1/fps), starting at a uniform phase in [0, 1/fps).
+"""
+from __future__ import annotations
+
+import dataclasses
+import threading
+import time
+
+import numpy as np
+
+from . import binding
+
+
+@dataclasses.dataclass
+class Arrival:
+    t: float        # seconds after the start of the run
+    radar: int
+    index: int      # arrival index over all radars, in time order
+
+
+def arrival_schedule(n_radars: int, fps: float, duration_s: float, seed: int) -> list[Arrival]:
+    """Arrivals of n_radars Poisson(fps) sources over [0, duration_s), in time order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    events = []
+    for r in range(n_radars):
+        t = rng.uniform(0.0, 1.0 / fps)
+        while t < duration_s:
+            events.append((t, r))
+            t += rng.exponential(1.0 / fps)
+    events.sort()
+    return [Arrival(t=t, radar=r, index=i) for i, (t, r) in enumerate(events)]
+
+
+def percentile(xs, q: float) -> float:
+    """Nearest-rank percentile (q in [0, 100]) of a non-empty sequence."""
+    a = np.sort(np.asarray(xs, dtype=np.float64))
+    if a.size == 0:
+        return float("nan")
+    k = int(np.ceil(q / 100.0 * a.size)) - 1
+    return float(a[min(max(k, 0), a.size - 1)])
+
+
+@dataclasses.dataclass
+class TrafficReport:
+    frames: int
+    clusters: int
+    evals: int
+    wall_s: float                 # first submit to last result
+    latency_ms: list[float]       # per frame: arrival (scheduled) -> result in host memory
+    server_latency_ms: list[float]  # per frame: submitted -> results in host memory (server clock)
+    batch_frames: list[int]
+    busy_retries: int
+    late_submits: int             # submits that started more than 1 ms after their arrival time
+    stats: dict
+
+    def summary(self) -> dict:
+        return {
+            "frames": self.frames, "clusters": self.clusters, "wall_s": self.wall_s,
+            "frames_per_s": self.frames / self.wall_s, "clusters_per_s": self.clusters / self.wall_s,
+            "evals_per_s": self.evals / self.wall_s,
+            "latency_ms": {"p50": percentile(self.latency_ms, 50),
+                           "p99": percentile(self.latency_ms, 99),
+                           "max": max(self.latency_ms)},
+            "server_latency_ms": {"p50": percentile(self.server_latency_ms, 50),
+                                  "p99": percentile(self.server_latency_ms, 99)},
+            "mean_batch_frames": float(np.mean(self.batch_frames)),
+            "busy_retries": self.busy_retries, "late_submits": self.late_submits,
+            "server": self.stats,
+        }
+
+
+def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_of,
+                n_hyp: int, *, paced: bool = True, keep_results: bool = False):
+    """Submit frames[a.radar] at each arrival's time (or as fast as the server
+    takes them when paced is False) and collect every result.
+
+    seed_of(arrival) gives the frame's hypothesis seed.  Returns (report,
+    results) where results maps arrival index -> result dict when keep_results.
+    """
+    evals_of = [int(n_hyp * np.diff(f.offsets.astype(np.int64))[np.diff(f.offsets) >= 2].sum())
+                for f in frames]
+    tickets: list[tuple[int, Arrival, float]] = []
+    cond = threading.Condition()
+    done_submitting = [False]
+    results = {}
+    lat, slat, bsz = [], [], []
+    counters = {"busy": 0, "late": 0}
+    errors = []
+
+    def submitter(t0):
+        for a in schedule:
+            if paced:
+                delay = t0 + a.t - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                elif delay < -1e-3:
+                    counters["late"] += 1
+            f = frames[a.radar]
+            while True:
+                try:
+                    tk = server.submit(f.theta, f.vd, f.offsets, seed_of(a))
+                    break
+                except binding.RVError as e:
+                    if e.code != binding.RV_ERR_BUSY:
+                        errors.append(e)
+                        return
+                    counters["busy"] += 1
+                    time.sleep(50e-6)
+            arrival = (t0 + a.t) if paced else time.perf_counter()
+            with cond:
+                tickets.append((tk, a, arrival))
+                cond.notify()
+        with cond:
+            done_submitting[0] = True
+            cond.notify()
+
+    t0 = time.perf_counter() + 0.01
+    th = threading.Thread(target=submitter, args=(t0,), daemon=True)
+    th.start()
+    got = 0
+    t_last = t0
+    while True:
+        with cond:
+            while got >= len(tickets) and not done_submitting[0]:
+                cond.wait()
+            if got >= len(tickets):
+                break
+            tk, a, arrival = tickets[got]
+        r = server.result(tk)
+        now = time.perf_counter()
+        t_last = now
+        lat.append((now - arrival) * 1e3)
+        tm = r["times"]
+        slat.append((tm["done_ns"] - tm["submitted_ns"]) * 1e-6)
+        bsz.append(tm["batch_frames"])
+        if keep_results:
+            results[a.index] = r
+        got += 1
+    th.join()
+    if errors:
+        raise errors[0]
+    clusters = sum(frames[a.radar].n_clusters for a in schedule)
+    evals = sum(evals_of[a.radar] for a in schedule)
+    rep = TrafficReport(frames=len(schedule), clusters=clusters, evals=evals,
+                        wall_s=max(t_last - t0, 1e-9), latency_ms=lat, server_latency_ms=slat,
+                        batch_frames=bsz, busy_retries=counters["busy"],
+                        late_submits=counters["late"], stats=server.stats())
+    return rep, results

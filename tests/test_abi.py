@@ -160,3 +160,31 @@ def test_batch_host_argument_checks(lib):
     assert call(K=0, N=0, ws=fake, ws_bytes=1 << 20) == 0
     assert lib.rv_graph_launch(None, None) == -1
     lib.rv_graph_destroy(None)
+
+
+def test_server_host_checks(lib):
+    from paper_2012_12618_amd import binding
+
+    cfg = binding.rv_server_config_default()
+    assert (cfg.n_hyp, cfg.max_batch_frames, cfg.n_streams) == (512, 64, 2)
+    assert cfg.hbm_budget_bytes == 16 << 30
+    # arena bytes of one frame: about 36 per point and 45 per cluster, 256-byte sections
+    b = binding.rv_server_frame_bytes(cfg, 700, 146_000)
+    assert 36 * 146_000 + 40 * 700 <= b <= 36 * 146_000 + 50 * 700 + 24 * 256
+    assert binding.rv_server_frame_bytes(cfg, -1, 5) == 0
+    h = ctypes.c_void_p()
+    for field, value, word in (("n_hyp", 0, "n_hyp"), ("tau", 0.0, "tau"),
+                               ("hbm_budget_bytes", 1000, "budget"),
+                               ("max_batch_frames", 0, "max_batch_frames"),
+                               ("n_streams", 9, "n_streams"),
+                               ("max_waiting_frames", 0, "max_waiting_frames")):
+        c = binding.rv_server_config_default()
+        setattr(c, field, value)
+        assert lib.rv_server_create(ctypes.byref(c), ctypes.byref(h)) == -1, field
+        assert word in lib.rv_last_error().decode() and not h.value
+    t = ctypes.c_uint64()
+    assert lib.rv_server_submit(None, None, None, None, 0, 0, 1, ctypes.byref(t)) == -1
+    assert lib.rv_server_wait(None, 1, 0) == -1
+    assert lib.rv_server_result(None, 1, None, None, None, None, None, None, None) == -1
+    assert lib.rv_server_stats(None, None) == -1
+    lib.rv_server_destroy(None)
