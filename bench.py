@@ -34,6 +34,10 @@ WORKLOAD_TEXT = {
     "batched": ("batched form: 256 frames of U{100..1500} clusters, log-uniform [8, 2048] points, "
                 "20% uniform outliers, 512 hypotheses, tau 0.15 m/s, FP32; one captured HIP graph "
                 "(staging, size-class ordering, persistent work-queue scoring, refit) per step"),
+    "served": ("served form: 64 simulated radars, each a Poisson(20 frames/s) source; frames of "
+               "U{200..1200} clusters, log-uniform [8, 1024] points, 25% uniform outliers, 512 "
+               "hypotheses, tau 0.15 m/s, FP32; frame server with a 16 GiB device budget, "
+               "continuous batching over launch slots; frames from and results to host memory"),
 }
 FRAME_WORKLOADS = ("dense", "small")
 
@@ -222,6 +226,118 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
     return 0
 
 
+def served_bench(args, torch, binding, synth, dev) -> int:
+    """Served form: paced arrivals for latency, then the same frames as fast as
+    the server takes them for throughput; the per-frame form (one frame per
+    launch, one slot) on the same traffic for comparison."""
+    from paper_2012_12618_amd import serve
+
+    name = args.workload
+    n_radars, fps = 64, 20.0
+    print(f"[bench] generating {n_radars} radar frames", file=sys.stderr, flush=True)
+    batch, n_hyp, tau = synth.make_batch_workload(name, n_frames=n_radars)
+    frames = [batch.frame_slice(f) for f in range(n_radars)]
+    schedule = serve.arrival_schedule(n_radars, fps, args.duration, seed=1)
+    warm = serve.arrival_schedule(n_radars, fps, 0.5, seed=2)
+    tuning = None
+    if args.tuning:
+        from paper_2012_12618_amd import tuner
+
+        tuning = tuner.load(args.tuning, torch.cuda.get_device_name(dev), n_hyp)
+
+    def make_server(max_batch, n_streams):
+        cfg = binding.rv_server_config_default()
+        cfg.n_hyp, cfg.tau = n_hyp, tau
+        cfg.hbm_budget_bytes = 16 << 30
+        cfg.max_batch_frames, cfg.n_streams = max_batch, n_streams
+        if tuning is not None:
+            cfg.tuning = tuning
+        return binding.RVServer(cfg)
+
+    def seed_of(a):
+        return synth.frame_seed(name, a.index)
+
+    out = {}
+    for form, (max_batch, n_streams) in (("served", (64, 2)), ("per_frame", (1, 1))):
+        server = make_server(max_batch, n_streams)
+        try:
+            print(f"[bench] {form}: warmup", file=sys.stderr, flush=True)
+            serve.run_traffic(server, frames, warm, seed_of, n_hyp, paced=False)
+            print(f"[bench] {form}: {len(schedule)} paced arrivals over {args.duration} s",
+                  file=sys.stderr, flush=True)
+            paced, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=True)
+            print(f"[bench] {form}: same arrivals unpaced", file=sys.stderr, flush=True)
+            if form == "served":
+                binding.rv_stage_times()
+                binding.rv_stage_timing(True)
+            sat, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=False)
+            if form == "served":
+                binding.rv_stage_timing(False)
+                out["stages"] = binding.rv_stage_times()
+        finally:
+            server.destroy()
+        out[form] = (paced.summary(), sat.summary(), sat)
+
+    paced_s, sat_s, sat = out["served"]
+    paced_f, sat_f, _ = out["per_frame"]
+    stage_ms, n_calls = out["stages"]
+    score_ms_total = stage_ms[binding.STAGE_NAMES.index("score")]
+    achieved_tflops = FLOP_PER_EVAL * sat.evals / (score_ms_total / 1e3) / 1e12 if score_ms_total else 0.0
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        print(f"[bench] oracle on the host, {threads} threads", file=sys.stderr, flush=True)
+        done, dt, ev_done, cl_done = oracle_baseline(
+            frames[:8], n_hyp, tau, lambda i: synth.frame_seed(name, 90_000 + i), threads)
+        cpu = {"value": ev_done / dt, "unit": "hyp-point evals/s", "cores": threads, "kind": "oracle",
+               "sample": (f"{done} radar frame(s) ({cl_done} clusters, {ev_done} evals), FP64, "
+                          f"{dt:.2f} s wall on {threads} threads"),
+               "clusters_per_s": cl_done / dt}
+
+    def brief(paced_sum, sat_sum):
+        return {"latency_ms": paced_sum["latency_ms"], "server_latency_ms": paced_sum["server_latency_ms"],
+                "offered_frames_per_s": paced_sum["frames_per_s"],
+                "mean_batch_frames_paced": paced_sum["mean_batch_frames"],
+                "saturated": {k: sat_sum[k] for k in ("frames_per_s", "clusters_per_s", "evals_per_s",
+                                                      "mean_batch_frames", "wall_s")}}
+
+    line = {
+        "metric": METRIC,
+        "value": sat_s["evals_per_s"],
+        "unit": "hyp-point evals/s",
+        "n_gpus": 1,
+        "steps": sat_s["frames"],
+        "warmup": len(warm),
+        "ms_per_step": sat_s["wall_s"] * 1e3 / max(sat_s["frames"], 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[name], "radars": n_radars, "fps_per_radar": fps,
+                   "duration_s": args.duration, "frames": len(schedule), "n_hyp": n_hyp, "tau": tau,
+                   "distinct_frame_contents": n_radars,
+                   "value_scope": "frames submitted back to back from host memory, results back "
+                                  "in host memory (copies included)"},
+        "clusters_per_s": sat_s["clusters_per_s"],
+        "latency_ms": paced_s["latency_ms"],
+        "served_form": brief(paced_s, sat_s),
+        "per_frame_form": brief(paced_f, sat_f),
+        "server": sat_s["server"],
+        "frac_fp32_valu_peak": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "kernel": "batch_score_kernel", "achieved": achieved_tflops,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None,
+                     "algorithmic_flop_per_launch": FLOP_PER_EVAL * sat.evals / max(n_calls, 1),
+                     "kernel_ms": score_ms_total / max(n_calls, 1), "launches": n_calls},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +350,8 @@ def main() -> int:
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: min(16, cpus))")
     ap.add_argument("--frames", type=int, default=0,
                     help="batched workload: number of frames (0: the workload's 256)")
+    ap.add_argument("--duration", type=float, default=5.0,
+                    help="served workload: seconds of simulated arrivals in the timed run")
     ap.add_argument("--tuning", default="",
                     help="batched workload: JSON tuning table written by paper_2012_12618_amd.tuner "
                          "(default: the library's default setting)")
@@ -261,6 +379,8 @@ def main() -> int:
     binding.load_library()
     dev = torch.device("cuda:0")
     name = args.workload
+    if name == "served":
+        return served_bench(args, torch, binding, synth, dev)
     if name not in FRAME_WORKLOADS:
         return batch_bench(args, torch, binding, synth, dev)
     print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)
