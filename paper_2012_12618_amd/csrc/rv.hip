@@ -578,14 +578,18 @@ __global__ __launch_bounds__(kRefitBlock) void refit_kernel(
 // The frames share one CSR: frame f owns clusters [frame_off[f], frame_off[f+1]).
 // A cluster draws its hypotheses with its frame's seed and its index within
 // the frame, so its result is bitwise the one a single-frame call gives.  The
-// scoring kernel is persistent: a fixed grid drains a device work queue of
-// (cluster, 256-hypothesis block) items, clusters largest first.
+// scoring kernel is persistent: a fixed grid drains device work queues of
+// (cluster, 256-hypothesis block) items, clusters largest first.  There is one
+// queue per XCD (its own 256-byte line): cluster j of the dispatch order
+// belongs to queue j % 8, and workgroup b serves queue b % 8 first (workgroups
+// are dispatched to the XCDs round-robin), so a cluster's blocks share one L2
+// and no counter is hammered by the whole chip; a workgroup whose queue is
+// empty takes items from the others.
 
 struct Batch {
     const int32_t *frame_off;  // [n_frames + 1]
     const uint64_t *seeds;     // [n_frames], device
     int64_t n_frames;
-    int32_t *frame_of;         // [n_clusters], filled by batch_prep_kernel
 };
 
 // Register rows per pass for each cluster-size bucket: bucket 0 holds n < 64,
@@ -593,6 +597,20 @@ struct Batch {
 struct Tuning {
     int32_t rows[RV_TUNE_BUCKETS];
 };
+
+// Everything the scoring and refit workgroups need about one cluster, at its
+// position in the dispatch order: one 32-byte load instead of a chain of
+// dependent loads (order, offsets, frame, seed).
+struct alignas(32) ItemDesc {
+    int32_t lo, n;         // point span; n = 0 when the offsets are bad
+    int32_t out;           // output index (the cluster's index in the batch)
+    uint32_t local;        // counter word 1: index within its frame
+    uint32_t key0, key1;   // Philox key: its frame's seed
+    int32_t ok;            // offsets valid
+    int32_t rows;          // register rows per pass for its size
+};
+
+constexpr int kQueueStride = 32;  // 64-bit counters: 256 bytes between queues
 
 __device__ __forceinline__ int size_bucket(int64_t n) {
     int b = 0;
@@ -615,33 +633,38 @@ __device__ __forceinline__ int64_t frame_of_cluster(const int32_t *__restrict__ 
     return lo;
 }
 
-__device__ __forceinline__ ClusterId batch_cluster(const Batch &bt, int64_t k) {
-    const int64_t f = bt.frame_of[k];
-    const uint64_t seed = bt.seeds[f];
+__device__ __forceinline__ Span desc_span(const ItemDesc &d) {
+    Span sp;
+    sp.lo = d.lo;
+    sp.n = d.n;
+    sp.ok = d.ok != 0;
+    return sp;
+}
+
+__device__ __forceinline__ ClusterId desc_id(const ItemDesc &d) {
     ClusterId id;
-    id.out = k;
-    id.local = (uint32_t)(k - bt.frame_off[f]);
-    id.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
-    id.key1 = (uint32_t)(seed >> 32);
+    id.out = d.out;
+    id.local = d.local;
+    id.key0 = d.key0;
+    id.key1 = d.key1;
     return id;
 }
 
-// Clears the size-class histogram and the work-queue head.
+// Clears the size-class histogram and the work queues.
 __global__ __launch_bounds__(kSizeClasses) void batch_init_kernel(
-    uint32_t *__restrict__ hist, unsigned long long *__restrict__ queue_head) {
+    uint32_t *__restrict__ hist, unsigned long long *__restrict__ queues) {
     hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *queue_head = 0;
+    if (threadIdx.x < kXcds) queues[threadIdx.x * kQueueStride] = 0;
 }
 
 // One thread per point: staging as in prep_kernel.  One thread per cluster:
-// clear its best key, find its frame, count it in its size class (per-block
-// LDS histogram, one global atomic per class and block).
+// clear its best key and count it in its size class (per-block LDS histogram,
+// one global atomic per class and block).
 __global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
     float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
     uint32_t *__restrict__ bits, int64_t n_words, const int32_t *__restrict__ off,
-    int64_t n_clusters, Batch bt, unsigned long long *__restrict__ best_key,
-    uint32_t *__restrict__ hist) {
+    int64_t n_clusters, unsigned long long *__restrict__ best_key, uint32_t *__restrict__ hist) {
     __shared__ uint32_t local[kSizeClasses];
     for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) local[c] = 0;
     __syncthreads();
@@ -658,7 +681,6 @@ __global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(
     if (bits != nullptr && p < n_words) bits[p] = 0u;
     if (p < n_clusters) {
         best_key[p] = 0;
-        bt.frame_of[p] = (int32_t)frame_of_cluster(bt.frame_off, bt.n_frames, p);
         atomicAdd(&local[size_class(cluster_span(off, p, n_points).n)], 1u);
     }
     __syncthreads();
@@ -677,11 +699,12 @@ __global__ __launch_bounds__(64) void batch_scan_kernel(uint32_t *__restrict__ h
     }
 }
 
-// Places every cluster in the dispatch order: one global atomic per class and
-// block reserves a range, LDS atomics rank the block's clusters inside it.
+// Places every cluster in the dispatch order (one global atomic per class and
+// block reserves a range, LDS atomics rank the block's clusters inside it) and
+// writes its descriptor there.
 __global__ __launch_bounds__(kPrepBlock) void batch_scatter_kernel(
-    const int32_t *__restrict__ off, int64_t n_clusters, int64_t n_points,
-    uint32_t *__restrict__ start, int32_t *__restrict__ order) {
+    const int32_t *__restrict__ off, int64_t n_clusters, int64_t n_points, Batch bt, Tuning tune,
+    uint32_t *__restrict__ start, ItemDesc *__restrict__ desc) {
     __shared__ uint32_t count[kSizeClasses];
     __shared__ uint32_t base[kSizeClasses];
     for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) count[c] = 0;
@@ -689,71 +712,79 @@ __global__ __launch_bounds__(kPrepBlock) void batch_scatter_kernel(
     const int64_t k = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
     int cls = -1;
     uint32_t rank = 0;
+    Span sp;
     if (k < n_clusters) {
-        cls = size_class(cluster_span(off, k, n_points).n);
+        sp = cluster_span(off, k, n_points);
+        cls = size_class(sp.n);
         rank = atomicAdd(&count[cls], 1u);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock)
         base[c] = count[c] != 0 ? atomicAdd(&start[c], count[c]) : 0u;
     __syncthreads();
-    if (cls >= 0) order[base[cls] + rank] = (int32_t)k;
+    if (cls < 0) return;
+    const int64_t f = frame_of_cluster(bt.frame_off, bt.n_frames, k);
+    const uint64_t seed = bt.seeds[f];
+    ItemDesc d;
+    d.lo = (int32_t)sp.lo;
+    d.n = (int32_t)sp.n;
+    d.out = (int32_t)k;
+    d.local = (uint32_t)(k - bt.frame_off[f]);
+    d.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    d.key1 = (uint32_t)(seed >> 32);
+    d.ok = sp.ok ? 1 : 0;
+    d.rows = tune.rows[size_bucket(sp.n)];
+    desc[base[cls] + rank] = d;
 }
 
-// Persistent scoring: each workgroup takes (cluster, block) items from the
-// queue until it is empty; every workgroup exits once the head passes the
-// last item.  The per-item tables (frame lookup, tuning) are copied to LDS
-// once, so they do not hold scalar registers through the scoring loop.  Seven
-// waves per SIMD keep the loop state out of spill code in the scoring passes.
+// Persistent scoring over the per-XCD queues (see above).  Every branch that
+// leads to or around a barrier in the item loop is taken on a wave-uniform
+// value (wave index, item read back with readfirstlane): with a per-lane guard
+// such as threadIdx.x == 0 the compiler may thread that guard across the
+// loop's back edge into a lane-masked inner loop that lane 0 leaves to fetch
+// the next item while lanes 1..63 wait on the old one.  Seven waves per SIMD
+// keep the loop state out of spill code in the scoring passes.
 __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))) void batch_score_kernel(
-    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
-    int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster, Batch bt, Points pts, float tau,
-    Tuning tune, unsigned long long *__restrict__ queue_head,
+    const ItemDesc *__restrict__ desc, int64_t n_clusters, int32_t n_hyp,
+    int32_t blocks_per_cluster, Points pts, float tau, unsigned long long *__restrict__ queues,
     unsigned long long *__restrict__ best_key, int32_t *__restrict__ hyp_counts) {
     __shared__ float4 s_hyp[kScoreBlock / 2];
     __shared__ unsigned long long s_key[kScoreBlock / kWave];
     __shared__ unsigned long long s_item;
-    __shared__ int32_t s_rows[RV_TUNE_BUCKETS];
-    __shared__ Batch s_bt;
-    if (threadIdx.x < RV_TUNE_BUCKETS) s_rows[threadIdx.x] = tune.rows[threadIdx.x];
-    if (threadIdx.x == 0) s_bt = bt;
-    const unsigned long long total = (unsigned long long)n_clusters * (unsigned long long)blocks_per_cluster;
-    // Every branch that leads to or around a barrier in this loop is taken on a
-    // wave-uniform value (wave index, item read back with readfirstlane).  With
-    // a per-lane guard such as threadIdx.x == 0 the compiler may thread that
-    // guard across the loop's back edge into a lane-masked inner loop that lane
-    // 0 leaves to fetch the next item while lanes 1..63 wait on the old one.
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
-    for (;;) {
-        if (wave == 0) {
-            unsigned long long got = 0;
-            if (lane == 0) got = atomicAdd(queue_head, 1ull);
-            s_item = uniform_u64(got);  // the same value from every lane of wave 0
+    const uint32_t home = blockIdx.x % kXcds;
+    const uint64_t bpc = (uint64_t)blocks_per_cluster;
+    for (uint32_t step = 0; step < kXcds; ++step) {
+        const uint32_t q = (home + step) % kXcds;
+        const int64_t clusters_q = n_clusters > (int64_t)q ? (n_clusters - q + kXcds - 1) / kXcds : 0;
+        const unsigned long long total = (unsigned long long)clusters_q * bpc;
+        for (;;) {
+            if (wave == 0) {
+                unsigned long long got = 0;
+                if (lane == 0) got = atomicAdd(&queues[q * kQueueStride], 1ull);
+                s_item = uniform_u64(got);  // the same value from every lane of wave 0
+            }
+            __syncthreads();
+            const unsigned long long item = uniform_u64(s_item);
+            __syncthreads();
+            if (item >= total) break;
+            const int64_t j = (int64_t)q + (int64_t)kXcds * (int64_t)(item / bpc);
+            const int b = (int)(item % bpc);
+            const ItemDesc d = desc[j];
+            score_block(desc_span(d), desc_id(d), b, n_hyp, pts, tau, d.rows, s_hyp, s_key,
+                        best_key, hyp_counts);
         }
-        __syncthreads();
-        const unsigned long long item = uniform_u64(s_item);
-        __syncthreads();
-        if (item >= total) break;
-        const int64_t j = (int64_t)(item / (unsigned long long)blocks_per_cluster);
-        const int b = (int)(item % (unsigned long long)blocks_per_cluster);
-        const int64_t k = order[j];
-        const Span sp = cluster_span(off, k, n_points);
-        const Batch btl = s_bt;
-        const int rows = s_rows[size_bucket(sp.n)];
-        score_block(sp, batch_cluster(btl, k), b, n_hyp, pts, tau, rows, s_hyp, s_key, best_key,
-                    hyp_counts);
     }
 }
 
 __global__ __launch_bounds__(kRefitBlock) void batch_refit_kernel(
-    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_points,
-    Batch bt, Points pts, const unsigned long long *__restrict__ best_key, float tau, Outputs o) {
+    const ItemDesc *__restrict__ desc, Points pts, const unsigned long long *__restrict__ best_key,
+    float tau, Outputs o) {
     __shared__ double s_sum[kRefitBlock / kWave][5];
     __shared__ int s_cnt[kRefitBlock / kWave][2];
-    const int64_t k = order[blockIdx.x];
-    refit_block(cluster_span(off, k, n_points), batch_cluster(bt, k), best_key[k], pts, tau, o,
-                s_sum, s_cnt);
+    const ItemDesc d = desc[blockIdx.x];
+    refit_block(desc_span(d), desc_id(d), best_key[d.out], pts, tau, o, s_sum, s_cnt);
 }
 
 __global__ __launch_bounds__(kPrepBlock) void philox_kernel(const uint32_t *__restrict__ ctr,
@@ -829,7 +860,7 @@ void keep_timed_call(const TimedCall &tc) {
 
 
 struct BatchLayout {
-    size_t cs32, v32, cs64, order, best_key, frame_of, hist, queue, total;
+    size_t cs32, v32, cs64, desc, best_key, hist, queues, total;
 };
 
 BatchLayout make_batch_layout(int64_t n_clusters, int64_t n_points) {
@@ -839,11 +870,10 @@ BatchLayout make_batch_layout(int64_t n_clusters, int64_t n_points) {
     L.cs32 = at; at = align_up(at + np * sizeof(float2));
     L.v32 = at; at = align_up(at + np * sizeof(float));
     L.cs64 = at; at = align_up(at + np * sizeof(double2));
-    L.order = at; at = align_up(at + nc * sizeof(int32_t));
+    L.desc = at; at = align_up(at + nc * sizeof(ItemDesc));
     L.best_key = at; at = align_up(at + nc * sizeof(unsigned long long));
-    L.frame_of = at; at = align_up(at + nc * sizeof(int32_t));
     L.hist = at; at = align_up(at + kSizeClasses * sizeof(uint32_t));
-    L.queue = at; at = align_up(at + sizeof(unsigned long long));
+    L.queues = at; at = align_up(at + kXcds * kQueueStride * sizeof(unsigned long long));
     L.total = at;
     return L;
 }
@@ -922,10 +952,10 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     float2 *cs32 = (float2 *)(ws + L.cs32);
     float *v32 = (float *)(ws + L.v32);
     double2 *cs64 = (double2 *)(ws + L.cs64);
-    int32_t *order = (int32_t *)(ws + L.order);
+    ItemDesc *desc = (ItemDesc *)(ws + L.desc);
     unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
     uint32_t *hist = (uint32_t *)(ws + L.hist);
-    unsigned long long *queue = (unsigned long long *)(ws + L.queue);
+    unsigned long long *queues = (unsigned long long *)(ws + L.queues);
     Points pts;
     pts.cs32 = cs32;
     pts.v32 = v32;
@@ -935,7 +965,6 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     bt.frame_off = a.frame_off;
     bt.seeds = a.seeds;
     bt.n_frames = a.n_frames;
-    bt.frame_of = (int32_t *)(ws + L.frame_of);
     Tuning tune;
     for (int b = 0; b < RV_TUNE_BUCKETS; ++b) tune.rows[b] = a.tuning.rows_max[b];
     const int64_t bpc = batch_blocks_per_cluster(a);
@@ -946,22 +975,21 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     TimedCall tc;
     const bool timed = allow_timing && take_timed_call(tc);
     if (timed) (void)hipEventRecord(tc.ev[0], st);
-    hipLaunchKernelGGL(batch_init_kernel, dim3(1), dim3(kSizeClasses), 0, st, hist, queue);
+    hipLaunchKernelGGL(batch_init_kernel, dim3(1), dim3(kSizeClasses), 0, st, hist, queues);
     hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)((prep_items + kPrepBlock - 1) / kPrepBlock)),
                        dim3(kPrepBlock), 0, st, a.theta, a.vd, a.n_points, cs32, v32, cs64,
-                       a.o.bits, n_words, a.off, a.n_clusters, bt, best_key, hist);
+                       a.o.bits, n_words, a.off, a.n_clusters, best_key, hist);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(64), 0, st, hist);
     hipLaunchKernelGGL(batch_scatter_kernel,
                        dim3((unsigned)((a.n_clusters + kPrepBlock - 1) / kPrepBlock)),
-                       dim3(kPrepBlock), 0, st, a.off, a.n_clusters, a.n_points, hist, order);
+                       dim3(kPrepBlock), 0, st, a.off, a.n_clusters, a.n_points, bt, tune, hist, desc);
     if (timed) (void)hipEventRecord(tc.ev[1], st);
-    hipLaunchKernelGGL(batch_score_kernel, dim3(grid), dim3(kScoreBlock), 0, st, a.off,
-                       (const int32_t *)order, a.n_clusters, a.n_points, a.n_hyp, (int32_t)bpc,
-                       bt, pts, a.tau, tune, queue, best_key, a.o.hyp_counts);
+    hipLaunchKernelGGL(batch_score_kernel, dim3(grid), dim3(kScoreBlock), 0, st,
+                       (const ItemDesc *)desc, a.n_clusters, a.n_hyp, (int32_t)bpc, pts, a.tau,
+                       queues, best_key, a.o.hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
     hipLaunchKernelGGL(batch_refit_kernel, dim3((unsigned)a.n_clusters), dim3(kRefitBlock), 0, st,
-                       a.off, (const int32_t *)order, a.n_points, bt, pts,
-                       (const unsigned long long *)best_key, a.tau, a.o);
+                       (const ItemDesc *)desc, pts, (const unsigned long long *)best_key, a.tau, a.o);
     if (timed) {
         (void)hipEventRecord(tc.ev[3], st);
         keep_timed_call(tc);

@@ -168,9 +168,10 @@ def test_server_host_checks(lib):
     cfg = binding.rv_server_config_default()
     assert (cfg.n_hyp, cfg.max_batch_frames, cfg.n_streams) == (512, 64, 2)
     assert cfg.hbm_budget_bytes == 16 << 30
-    # arena bytes of one frame: about 36 per point and 45 per cluster, 256-byte sections
+    # arena bytes of one frame: 36 per point (inputs 8, staging 28) and 65 per cluster
+    # (offsets 4, descriptor 32, best key 8, outputs 21), plus 256-byte sections and queues
     b = binding.rv_server_frame_bytes(cfg, 700, 146_000)
-    assert 36 * 146_000 + 40 * 700 <= b <= 36 * 146_000 + 50 * 700 + 24 * 256
+    assert 36 * 146_000 + 65 * 700 <= b <= 36 * 146_000 + 65 * 700 + 24 * 256 + 2560
     assert binding.rv_server_frame_bytes(cfg, -1, 5) == 0
     h = ctypes.c_void_p()
     for field, value, word in (("n_hyp", 0, "n_hyp"), ("tau", 0.0, "tau"),
