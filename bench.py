@@ -70,7 +70,7 @@ def percentile(xs, q):
     return xs[i]
 
 
-def oracle_baseline(frames, n_hyp, tau, seed_of, threads, budget_s=1.5, max_frames=64):
+def oracle_baseline(frames, n_hyp, tau, seed_of, threads, budget_s=1.5, max_frames=4096):
     """The FP64 oracle on whole frames (fresh seeds) until about budget_s of wall time."""
     import oracle
 
