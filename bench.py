@@ -70,6 +70,20 @@ def percentile(xs, q):
     return xs[i]
 
 
+def calibration_copy(torch, dev, mb: int) -> None:
+    """One device-to-device copy of mb MiB (outside any timed region): the
+    kernel of known traffic that scales the HBM byte counters."""
+    if mb <= 0:
+        return
+    nbytes = mb << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    print(f"[bench] calibration copy of {nbytes} bytes", file=sys.stderr, flush=True)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def oracle_baseline(frames, n_hyp, tau, seed_of, threads, budget_s=1.5, max_frames=4096):
     """The FP64 oracle on whole frames (fresh seeds) until about budget_s of wall time."""
     import oracle
@@ -177,6 +191,7 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
     torch.cuda.synchronize()
     per_frame_ms = ev0.elapsed_time(ev1) / reps
     del per
+    calibration_copy(torch, dev, args.copy_calibration_mb)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -465,14 +480,7 @@ def main() -> int:
         lat.append((time.perf_counter() - t0) * 1e3)
     del slots
 
-    if args.copy_calibration_mb > 0:
-        nbytes = args.copy_calibration_mb << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        print(f"[bench] calibration copy of {nbytes} bytes", file=sys.stderr, flush=True)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(torch, dev, args.copy_calibration_mb)
 
     cpu = None
     if not args.no_cpu_baseline:

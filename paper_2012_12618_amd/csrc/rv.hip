@@ -347,6 +347,11 @@ struct ClusterId {
 // index) key over its valid hypotheses is merged into best_key with a 64-bit
 // atomic maximum, whose result does not depend on the order of the blocks.
 // Called by all threads of the block; contains block barriers.
+// kUniformTail: the block's key is merged under a wave-uniform guard (needed
+// where score_block runs inside a loop with barriers, see batch_score_kernel);
+// otherwise under threadIdx.x == 0, which leaves the single-pass kernel's
+// register allocation free of spills.
+template <bool kUniformTail>
 __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_t n_hyp,
                                             const Points &pts, float tau, int rows_max,
                                             float4 *s_hyp, unsigned long long *s_key,
@@ -389,9 +394,14 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
     key = wave_max_u64(key);
     if (lane == 0) s_key[wave] = key;
     __syncthreads();
-    if (wave == 0) {  // wave-uniform guard; one lane merges the block's key
+    if (kUniformTail) {
+        if (wave == 0) {  // wave-uniform guard; one lane merges the block's key
+            for (int w = 1; w < kScoreBlock / kWave; ++w) key = s_key[w] > key ? s_key[w] : key;
+            if (lane == 0 && key != 0) atomicMax(&best_key[id.out], key);
+        }
+    } else if (tid == 0) {
         for (int w = 1; w < kScoreBlock / kWave; ++w) key = s_key[w] > key ? s_key[w] : key;
-        if (lane == 0 && key != 0) atomicMax(&best_key[id.out], key);
+        if (key != 0) atomicMax(&best_key[id.out], key);
     }
 }
 
@@ -553,8 +563,8 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     id.local = (uint32_t)k;
     id.key0 = key0;
     id.key1 = key1;
-    score_block(cluster_span(off, k, n_points), id, b, n_hyp, pts, tau, kRowsMax, s_hyp, s_key,
-                best_key, hyp_counts);
+    score_block<false>(cluster_span(off, k, n_points), id, b, n_hyp, pts, tau, kRowsMax, s_hyp,
+                       s_key, best_key, hyp_counts);
 }
 
 // One workgroup per cluster, clusters in the planned order.
@@ -772,8 +782,8 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))
             const int64_t j = (int64_t)q + (int64_t)kXcds * (int64_t)(item / bpc);
             const int b = (int)(item % bpc);
             const ItemDesc d = desc[j];
-            score_block(desc_span(d), desc_id(d), b, n_hyp, pts, tau, d.rows, s_hyp, s_key,
-                        best_key, hyp_counts);
+            score_block<true>(desc_span(d), desc_id(d), b, n_hyp, pts, tau, d.rows, s_hyp, s_key,
+                              best_key, hyp_counts);
         }
     }
 }
