@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rv_oracle.c")
+_SRC_PAPER = os.path.join(_HERE, "rv_oracle_paper.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Per-cluster status codes (same meaning as the estimator's).
@@ -36,12 +37,13 @@ FP32_BAND_REL = 1.5 * 2.0**-24  # relative band covering a float32 residual eval
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no FP contraction, no fast-math)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_PAPER))
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= newest:
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = [
         "gcc", "-O2", "-march=x86-64-v2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-        "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm", "-lpthread",
+        "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, _SRC_PAPER, "-lm", "-lpthread",
     ]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
@@ -77,6 +79,13 @@ def _load():
                                           P, P, P, P, P, P, P, P]
     lib.oracle_all_pairs_best.restype = i32
     lib.oracle_all_pairs_best.argtypes = [P, P, i32, f32, P, P]
+    lib.oracle_estimate_velocity_paper.restype = ctypes.c_int
+    lib.oracle_estimate_velocity_paper.argtypes = [P, P, P, i64, i64, i32, u64,
+                                                   P, P, P, P, P, P, P, P, P, P]
+    lib.oracle_median.restype = f64
+    lib.oracle_median.argtypes = [P, i64]
+    lib.oracle_paper_line_distance.restype = f64
+    lib.oracle_paper_line_distance.argtypes = [f64] * 6
     _lib = lib
     return lib
 
@@ -237,3 +246,59 @@ def all_pairs_best(theta, vd, tau: float):
     counts = np.full((n, n), -1, dtype=np.int32)
     best = lib.oracle_all_pairs_best(_ptr(th), _ptr(v), n, float(tau), _ptr(mask), _ptr(counts))
     return int(best), mask.astype(bool), counts
+
+
+# ---- paper-literal variant (Sec. 3.1 Alg. 1 with Eq. 5's threshold) ----------
+
+@dataclass
+class PaperResult:
+    vx: np.ndarray          # float64 [K]
+    vy: np.ndarray
+    heading: np.ndarray
+    thresh: np.ndarray      # float64 [K]: MAD of the normalised Doppler values
+    n_inliers: np.ndarray   # int32 [K]
+    status: np.ndarray      # uint8 [K]
+    best_hyp: np.ndarray    # int32 [K]
+    inlier_mask: np.ndarray | None  # uint8 [N]
+    hyp_valid: np.ndarray | None    # uint8 [K, H]
+    hyp_count: np.ndarray | None    # int32 [K, H]
+
+
+def estimate_velocity_paper(theta, vd, offsets, n_hyp: int, seed: int, *, want_mask: bool = True,
+                            debug: bool = False) -> PaperResult:
+    """The paper-literal estimate (rv_oracle_paper.c): min-max normalisation,
+    MAD threshold, line through two seeds, perpendicular distance <= thresh,
+    most inliers, least-squares refit, atan2."""
+    lib = _load()
+    theta = np.ascontiguousarray(theta, np.float32)
+    vd = np.ascontiguousarray(vd, np.float32)
+    offsets = np.ascontiguousarray(offsets, np.int32)
+    K, N = len(offsets) - 1, len(theta)
+    out = dict(vx=np.empty(K), vy=np.empty(K), heading=np.empty(K), thresh=np.empty(K),
+               n_inliers=np.empty(K, np.int32), status=np.empty(K, np.uint8),
+               best_hyp=np.empty(K, np.int32))
+    mask = np.empty(max(N, 1), np.uint8) if want_mask else None
+    hv = np.empty((max(K, 1), n_hyp), np.uint8) if debug else None
+    hc = np.empty((max(K, 1), n_hyp), np.int32) if debug else None
+    rc = lib.oracle_estimate_velocity_paper(
+        _ptr(theta), _ptr(vd), _ptr(offsets), K, N, int(n_hyp), int(seed) & 0xFFFFFFFFFFFFFFFF,
+        _ptr(out["vx"]), _ptr(out["vy"]), _ptr(out["heading"]), _ptr(out["thresh"]),
+        _ptr(out["n_inliers"]), _ptr(out["status"]), _ptr(out["best_hyp"]),
+        _ptr(mask) if mask is not None else None, _ptr(hv) if hv is not None else None,
+        _ptr(hc) if hc is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_estimate_velocity_paper: bad arguments")
+    return PaperResult(**out, inlier_mask=None if mask is None else mask[:N],
+                       hyp_valid=None if hv is None else hv[:K],
+                       hyp_count=None if hc is None else hc[:K])
+
+
+def median(values) -> float:
+    """The oracle's median (mean of the two middle values for an even count)."""
+    a = np.array(values, dtype=np.float64)
+    return float(_load().oracle_median(_ptr(a), a.size))
+
+
+def paper_line_distance(x1, y1, x2, y2, px, py) -> float:
+    """Alg. 1's distance of (px, py) to the line through (x1, y1), (x2, y2)."""
+    return float(_load().oracle_paper_line_distance(x1, y1, x2, y2, px, py))
