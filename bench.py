@@ -39,6 +39,10 @@ WORKLOAD_TEXT = {
                "hypotheses, tau 0.15 m/s, FP32; frame server with a 16 GiB device budget, "
                "continuous batching over launch slots; frames from and results to host memory"),
 }
+WORKLOAD_TEXT["paper-sweep"] = (
+    "paper-literal variant (normalised line fit, MAD threshold, <= test, least-squares refit) "
+    "on the shapes of the paper's Tables I and II: {8, 16, 32, 64} clusters x {100, 150} points, "
+    "20% uniform outliers, 256 trials per cluster, FP64")
 FRAME_WORKLOADS = ("dense", "small")
 
 
@@ -353,6 +357,114 @@ def served_bench(args, torch, binding, synth, dev) -> int:
     return 0
 
 
+def paper_sweep_bench(args, torch, binding, synth, dev) -> int:
+    """Tables I and II of the paper: per shape, GPU time of the trial stage
+    (normalisation, threshold and trials: Table I's kernel) and of the refit
+    (Table II's kernel), from the library's events, over fresh seeds."""
+    import numpy as np
+
+    H = 256
+    rows = []
+    stream = torch.cuda.current_stream(dev)
+    for clusters, points in synth.TABLE_SHAPES:
+        f = synth.table_frame(clusters, points)
+        t = torch.from_numpy(f.theta).to(dev)
+        v = torch.from_numpy(f.vd).to(dev)
+        o = torch.from_numpy(f.offsets).to(dev)
+        for i in range(args.warmup):
+            binding.rv_estimate_velocity_paper(t, v, o, H, synth.ransac_seed("paper", i), stream=stream)
+        torch.cuda.synchronize()
+        binding.rv_stage_times()
+        binding.rv_stage_timing(True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for i in range(args.steps):
+            binding.rv_estimate_velocity_paper(t, v, o, H, synth.ransac_seed("paper", 1000 + i),
+                                               stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        binding.rv_stage_timing(False)
+        ms, n = binding.rv_stage_times()
+        stage = [x / max(n, 1) for x in ms]
+        row = {"clusters": clusters, "points": points,
+               "gpu_ms_per_frame": ev0.elapsed_time(ev1) / args.steps,
+               "gpu_ransac_ms": stage[0] + stage[1], "gpu_lsq_ms": stage[2]}
+        if args.host_comparators:
+            row.update(host_comparators(f, H))
+        rows.append(row)
+        print(f"[bench] paper {clusters}x{points}: {row['gpu_ms_per_frame']:.4f} ms/frame",
+              file=sys.stderr, flush=True)
+    big = rows[-1]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        f = synth.table_frame(64, 150)
+        done, dt = 0, 0.0
+        while done == 0 or (dt < 1.5 and done < 4096):
+            t0 = time.perf_counter()
+            oracle.estimate_velocity_paper(f.theta, f.vd, f.offsets, H, 50_000 + done, want_mask=False)
+            dt += time.perf_counter() - t0
+            done += 1
+        cpu = {"value": done * f.n_clusters / dt, "unit": "clusters/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} frame(s) of 64 clusters x 150 points, H = {H}, FP64, {dt:.2f} s on one thread"}
+    line = {
+        "metric": METRIC,
+        "value": big["clusters"] / (big["gpu_ms_per_frame"] / 1e3),
+        "unit": "clusters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": big["gpu_ms_per_frame"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["paper-sweep"], "n_hyp": H,
+                   "value_scope": "64 clusters x 150 points, whole estimate per frame"},
+        "table": rows,
+        "paper_table_ms": {"ransac_gtx1060": {"8x100": 1.64, "8x150": 1.77, "16x100": 1.68,
+                                              "16x150": 1.82, "32x100": 1.73, "32x150": 1.89,
+                                              "64x100": 1.98, "64x150": 2.23},
+                           "lsq_gtx1060": {"8x100": 1.81, "8x150": 1.83, "16x100": 1.81,
+                                           "16x150": 1.83, "32x100": 1.81, "32x150": 1.83,
+                                           "64x100": 1.81, "64x150": 1.83},
+                           "note": "the paper's own timings on its hardware, context only"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def host_comparators(f, H):
+    """The paper's host comparators on one frame: scikit-learn RANSACRegressor of
+    v_d on theta per cluster (max_trials = H) and numpy.linalg.pinv per cluster."""
+    import numpy as np
+
+    out = {}
+    try:
+        from sklearn.linear_model import RANSACRegressor
+
+        t0 = time.perf_counter()
+        for k in range(f.n_clusters):
+            a, b = f.offsets[k], f.offsets[k + 1]
+            RANSACRegressor(max_trials=H, random_state=k).fit(
+                f.theta[a:b, None].astype(np.float64), f.vd[a:b].astype(np.float64))
+        out["sklearn_ransac_ms"] = (time.perf_counter() - t0) * 1e3
+    except ImportError:
+        out["sklearn_ransac_ms"] = None
+    t0 = time.perf_counter()
+    for k in range(f.n_clusters):
+        a, b = f.offsets[k], f.offsets[k + 1]
+        th = f.theta[a:b].astype(np.float64)
+        A = np.stack([np.cos(th), np.sin(th)], axis=1)
+        np.linalg.pinv(A) @ f.vd[a:b].astype(np.float64)
+    out["numpy_pinv_ms"] = (time.perf_counter() - t0) * 1e3
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,6 +479,9 @@ def main() -> int:
                     help="batched workload: number of frames (0: the workload's 256)")
     ap.add_argument("--duration", type=float, default=5.0,
                     help="served workload: seconds of simulated arrivals in the timed run")
+    ap.add_argument("--host-comparators", action="store_true",
+                    help="paper-sweep: also time scikit-learn RANSACRegressor and numpy pinv per "
+                         "cluster on the host (the paper's Table I/II comparators; context only)")
     ap.add_argument("--tuning", default="",
                     help="batched workload: JSON tuning table written by paper_2012_12618_amd.tuner "
                          "(default: the library's default setting)")
@@ -396,6 +511,8 @@ def main() -> int:
     name = args.workload
     if name == "served":
         return served_bench(args, torch, binding, synth, dev)
+    if name == "paper-sweep":
+        return paper_sweep_bench(args, torch, binding, synth, dev)
     if name not in FRAME_WORKLOADS:
         return batch_bench(args, torch, binding, synth, dev)
     print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)

@@ -51,9 +51,15 @@ enum {
     RV_CLUSTER_ALL_DEGENERATE = 2, /* no valid seed pair among the n_hyp draws */
     RV_CLUSTER_SINGULAR_REFIT = 3, /* the kept inlier set has fewer than two points
                                       or a non-positive normal-equation determinant */
-    RV_CLUSTER_BAD_OFFSETS = 4     /* offsets[k] < 0, offsets[k+1] < offsets[k], or
+    RV_CLUSTER_BAD_OFFSETS = 4,    /* offsets[k] < 0, offsets[k+1] < offsets[k], or
                                       offsets[k+1] > n_points */
+    RV_CLUSTER_TOO_LARGE = 5       /* paper-literal variant only: more than
+                                      RV_PAPER_MAX_POINTS points */
 };
+
+/* Largest cluster the paper-literal variant handles (its medians are sorted in
+   on-chip memory). */
+#define RV_PAPER_MAX_POINTS 4096
 
 /* A seed pair is degenerate (its hypothesis invalid) when its two azimuths,
    promoted to double, differ by less than this many radians. */
@@ -181,6 +187,37 @@ int rv_graph_launch(rv_graph_t *graph, void *stream);
 void rv_graph_destroy(rv_graph_t *graph);
 
 /*
+ * Paper-literal variant of the inlier kernel (Sec. 3.1, Alg. 1, Eq. 5),
+ * followed by the same least-squares refit and heading (Sec. 3.2, Eq. 7,
+ * Alg. 2, Eq. 8).  Per cluster, in FP64:
+ *   - azimuth and Doppler are mapped onto [0, 1] by the cluster's min and max
+ *     (Alg. 1's normalize(); a zero span maps to 0);
+ *   - thresh = median |y - median(y)| of the normalised Doppler values y
+ *     (Eq. 5, read as the median absolute deviation its text names; the median
+ *     of an even count is the mean of the two middle values);
+ *   - trial h draws its seed pair exactly as rv_estimate_velocity does (same
+ *     seed, counter (h, k, 0, 0), same validity rule) and fits the line
+ *     y = m x + c through the two normalised seeds;
+ *   - a point is an inlier when |(-m) x + 1 y + (-c)| / sqrt(m^2 + 1) <= thresh
+ *     (Alg. 1's distance and test, evaluated as written, no contraction);
+ *   - the valid trial with the most inliers is kept (ties: lowest h), and
+ *     (vx, vy) is the least-squares solution of v_d = vx cos + vy sin over its
+ *     inliers; heading = atan2(vy, vx).
+ * Arguments as rv_estimate_velocity without tau; thresh[n_clusters] (FP64,
+ * device, nullable) receives each cluster's threshold.  Clusters of more than
+ * RV_PAPER_MAX_POINTS points get RV_CLUSTER_TOO_LARGE.  The workspace must hold
+ * rv_paper_workspace_bytes(n_clusters, n_points, n_hyp) bytes, 256-byte
+ * aligned (16 B per point + 16 B per cluster).
+ */
+size_t rv_paper_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t n_hyp);
+int rv_estimate_velocity_paper(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                               int64_t n_clusters, int64_t n_points, int32_t n_hyp, uint64_t seed,
+                               float *vx, float *vy, float *heading, int32_t *n_inliers,
+                               uint8_t *status, double *thresh, uint32_t *inlier_bits,
+                               int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/*
  * Frame server (request loop with continuous batching).
  *
  * A server owns one device arena of hbm_budget_bytes (allocated once, at
@@ -280,8 +317,10 @@ const char *rv_last_error(void);
 
 /*
  * Instrumentation (not part of the estimate).  While enabled, every
- * rv_estimate_velocity or rv_estimate_velocity_batch call (not graph replays)
- * records HIP events around its kernels on its stream.  rv_stage_times waits for the recorded events, writes
+ * rv_estimate_velocity, rv_estimate_velocity_batch or rv_estimate_velocity_paper
+ * call (not graph replays) records HIP events around its kernels on its stream
+ * (for the paper-literal variant the stages are: normalisation and threshold,
+ * trials, refit).  rv_stage_times waits for the recorded events, writes
  * the summed milliseconds per stage (ms[0]: point staging and dispatch
  * planning, ms[1]: hypotheses and scoring, ms[2]: selection and refit) and the
  * number of calls into *n_calls, and clears the record.  Returns RV_OK or

@@ -26,6 +26,8 @@ RV_CLUSTER_TOO_FEW_POINTS = 1
 RV_CLUSTER_ALL_DEGENERATE = 2
 RV_CLUSTER_SINGULAR_REFIT = 3
 RV_CLUSTER_BAD_OFFSETS = 4
+RV_CLUSTER_TOO_LARGE = 5
+RV_PAPER_MAX_POINTS = 4096
 
 RV_MIN_SEED_SEPARATION = 1e-3
 RV_NEAR_TAU_WINDOW = 1e-5
@@ -132,6 +134,11 @@ def load_library() -> ctypes.CDLL:
     lib.rv_graph_launch.argtypes = [P, P]
     lib.rv_graph_destroy.restype = None
     lib.rv_graph_destroy.argtypes = [P]
+    lib.rv_paper_workspace_bytes.restype = ctypes.c_size_t
+    lib.rv_paper_workspace_bytes.argtypes = [i64, i64, i32]
+    lib.rv_estimate_velocity_paper.restype = ctypes.c_int
+    lib.rv_estimate_velocity_paper.argtypes = [P, P, P, i64, i64, i32, ctypes.c_uint64,
+                                               P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
     lib.rv_server_config_default.restype = None
     lib.rv_server_config_default.argtypes = [P]
     lib.rv_server_frame_bytes.restype = ctypes.c_size_t
@@ -409,6 +416,50 @@ def rv_graph_capture_batch(theta, vd, offsets, frame_offsets, seeds, n_hyp: int,
     handle = ctypes.c_void_p()
     _check(lib.rv_graph_capture_batch(*args, ctypes.byref(handle)))
     return RVGraph(handle, (theta, vd, offsets, frame_offsets, seeds, out, tune))
+
+
+# ---- paper-literal variant ----------------------------------------------------
+
+def rv_paper_workspace_bytes(n_clusters: int, n_points: int, n_hyp: int) -> int:
+    return int(load_library().rv_paper_workspace_bytes(int(n_clusters), int(n_points), int(n_hyp)))
+
+
+def rv_estimate_velocity_paper(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
+                               n_hyp: int, seed: int, *, want_bits: bool = False,
+                               debug: bool = False, stream=None) -> dict:
+    """Paper-literal inlier kernel (normalised line fit, MAD threshold, <= test)
+    and the least-squares refit; outputs as rv_estimate_velocity plus ``thresh``
+    (float64 per cluster)."""
+    lib = load_library()
+    device = theta.device
+    if device.type != "cuda":
+        raise ValueError("theta must be a GPU tensor")
+    n_points, n_clusters = int(theta.numel()), int(offsets.numel()) - 1
+    if n_clusters < 0 or int(vd.numel()) != n_points:
+        raise ValueError("offsets needs n_clusters + 1 entries; theta and vd must match")
+    out = allocate_outputs(n_clusters, n_points, n_hyp, device, want_near=False,
+                           want_bits=want_bits, debug=debug)
+    out.pop("workspace")
+    out["thresh"] = torch.empty(n_clusters, dtype=torch.float64, device=device)
+    ws = torch.empty(max(rv_paper_workspace_bytes(n_clusters, n_points, n_hyp), 1),
+                     dtype=torch.uint8, device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    _check(lib.rv_estimate_velocity_paper(
+        _dev_ptr(theta, torch.float32, device, "theta"), _dev_ptr(vd, torch.float32, device, "vd"),
+        _dev_ptr(offsets, torch.int32, device, "offsets"), n_clusters, n_points, int(n_hyp),
+        int(seed) & 0xFFFFFFFFFFFFFFFF,
+        _dev_ptr(out["vx"], torch.float32, device, "vx"), _dev_ptr(out["vy"], torch.float32, device, "vy"),
+        _dev_ptr(out["heading"], torch.float32, device, "heading"),
+        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
+        _dev_ptr(out["status"], torch.uint8, device, "status"),
+        _dev_ptr(out["thresh"], torch.float64, device, "thresh"),
+        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
+        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
+        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+        ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream)))
+    out["_workspace"] = ws  # keep alive until the stream has used it
+    return out
 
 
 # ---- frame server -----------------------------------------------------------

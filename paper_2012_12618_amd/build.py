@@ -1,5 +1,6 @@
 """Build the gfx950 shared library ``_lib/librv.so`` from ``csrc/rv.hip`` (kernels
-and estimator entry points) and ``csrc/rv_server.cpp`` (frame server).
+and estimator entry points), ``csrc/rv_paper.hip`` (paper-literal variant) and
+``csrc/rv_server.cpp`` (frame server).
 
 Usage: ``python -m paper_2012_12618_amd.build`` (also called by the repository's
 ``__graft_entry__.build()``).  hipcc cross-compiles for gfx950 without a GPU.
@@ -13,7 +14,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", "rv.hip"), os.path.join(HERE, "csrc", "rv_server.cpp")]
+SRCS = [os.path.join(HERE, "csrc", n) for n in ("rv.hip", "rv_paper.hip", "rv_server.cpp")]
 INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "librv.so")

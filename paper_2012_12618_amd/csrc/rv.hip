@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "rv.h"
+#include "rv_device.h"
 #include "rv_internal.h"
 
 // v_writelane_b32: write a wave-uniform value into one lane of a VGPR (the
@@ -53,11 +54,35 @@ int fail(int code, const char *fmt, ...) {
     va_end(ap);
     return code;
 }
+
+// Stage timing (rv_stage_timing / rv_stage_times): events recorded around the
+// kernels of a call.
+std::mutex g_timing_mutex;
+bool g_timing = false;
+std::vector<TimedCall> g_pending;   // recorded, not yet read
+std::vector<TimedCall> g_free;      // reusable event sets
+
+bool take_timed_call(TimedCall &tc) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    if (!g_timing) return false;
+    if (!g_free.empty()) {
+        tc = g_free.back();
+        g_free.pop_back();
+        return true;
+    }
+    for (int i = 0; i <= kStages; ++i)
+        if (hipEventCreate(&tc.ev[i]) != hipSuccess) return false;
+    return true;
+}
+
+void keep_timed_call(const TimedCall &tc) {
+    std::lock_guard<std::mutex> lock(g_timing_mutex);
+    g_pending.push_back(tc);
+}
 }  // namespace rv_internal
 
 namespace {
 
-constexpr int kWave = 64;
 constexpr int kScoreBlock = 256;        // score: 4 waves x 64 hypotheses, one per thread
 constexpr int kRefitBlock = 256;
 constexpr int kXcds = 8;                // MI355X: 8 XCDs, workgroups dealt round-robin
@@ -66,58 +91,9 @@ constexpr int kRowsMax = 16;            // rows of 64 points held in registers p
 constexpr int kHypGroup = 4;            // hypotheses per LDS fetch in the scoring loop
 constexpr int kSizeClasses = 128;       // quarter-octave size classes for the dispatch order
 constexpr int64_t kPlanMaxClusters = 1 << 16;  // above this, clusters run in index order
-constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
-constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
-constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
-constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
-
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------
-
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
-// mixed into the counter words, key advanced by the Weyl constants between rounds.
-__device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        if (round > 0) {
-            k0 += kPhiloxW0;
-            k1 += kPhiloxW1;
-        }
-        // one 32x32->64 multiply-add instruction per product
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * x.x;
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * x.z;
-        x = make_uint4((uint32_t)(p1 >> 32) ^ x.y ^ k0, (uint32_t)p1,
-                       (uint32_t)(p0 >> 32) ^ x.w ^ k1, (uint32_t)p0);
-    }
-    return x;
-}
-
-// Two distinct indices in [0, n) from two uniform words (multiply-shift map;
-// the second index skips the first).  Requires 2 <= n < 2^31.
-__device__ __forceinline__ void seed_pair(uint32_t u0, uint32_t u1, uint32_t n, uint32_t &i,
-                                          uint32_t &j) {
-    i = (uint32_t)(((uint64_t)u0 * n) >> 32);
-    const uint32_t b = (uint32_t)(((uint64_t)u1 * (n - 1u)) >> 32);
-    j = b + (b >= i ? 1u : 0u);
-}
-
-struct Span {
-    int64_t lo;
-    int64_t n;
-    bool ok;
-};
-
-__device__ __forceinline__ Span cluster_span(const int32_t *__restrict__ off, int64_t k,
-                                             int64_t n_points) {
-    const int64_t a = off[k];
-    const int64_t b = off[k + 1];
-    Span s;
-    s.ok = a >= 0 && b >= a && b <= n_points;
-    s.lo = s.ok ? a : 0;
-    s.n = s.ok ? b - a : 0;
-    return s;
-}
 
 // Staged points: float32 (cos, sin) and v_d for scoring (v_d = +inf marks a
 // point whose azimuth or Doppler value is not finite), FP64 (cos, sin) for the
@@ -157,34 +133,6 @@ __device__ __forceinline__ Hypothesis make_hypothesis(const Points &pts, Span sp
     hy.vx = (dvi * sj - dvj * si) * inv_det;
     hy.vy = (ci * dvj - cj * dvi) * inv_det;
     return hy;
-}
-
-// Lane 0's value of v in every lane, as a wave-uniform (scalar) value.
-__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -818,6 +766,14 @@ __global__ __launch_bounds__(kPrepBlock) void philox_kernel(const uint32_t *__re
 
 using rv_internal::fail;
 using rv_internal::g_error;
+using rv_internal::g_free;
+using rv_internal::g_pending;
+using rv_internal::g_timing;
+using rv_internal::g_timing_mutex;
+using rv_internal::keep_timed_call;
+using rv_internal::kStages;
+using rv_internal::take_timed_call;
+using rv_internal::TimedCall;
 
 constexpr size_t kAlign = 256;
 
@@ -841,32 +797,6 @@ Layout make_layout(int64_t n_clusters, int64_t n_points) {
 }
 
 // Stage timing: events recorded around each kernel of each call.
-constexpr int kStages = 3;
-struct TimedCall {
-    hipEvent_t ev[kStages + 1];
-};
-std::mutex g_timing_mutex;
-bool g_timing = false;
-std::vector<TimedCall> g_pending;   // recorded, not yet read
-std::vector<TimedCall> g_free;      // reusable event sets
-
-bool take_timed_call(TimedCall &tc) {
-    std::lock_guard<std::mutex> lock(g_timing_mutex);
-    if (!g_timing) return false;
-    if (!g_free.empty()) {
-        tc = g_free.back();
-        g_free.pop_back();
-        return true;
-    }
-    for (int i = 0; i <= kStages; ++i)
-        if (hipEventCreate(&tc.ev[i]) != hipSuccess) return false;
-    return true;
-}
-
-void keep_timed_call(const TimedCall &tc) {
-    std::lock_guard<std::mutex> lock(g_timing_mutex);
-    g_pending.push_back(tc);
-}
 
 
 struct BatchLayout {

@@ -1,0 +1,487 @@
+// rv_paper.hip -- gfx950 kernels and host entry point of the paper-literal
+// variant of the inlier kernel (Sec. 3.1, Alg. 1 with Eq. 5's threshold),
+// followed by the least-squares kernel (Sec. 3.2, Eq. 7, Alg. 2, Eq. 8).
+//
+// Per cluster:
+//   stats   one workgroup: per-cluster min-max normalisation of azimuth and
+//           Doppler onto [0, 1] (Alg. 1's normalize(); a zero span maps to 0),
+//           then the median absolute deviation of the normalised Doppler
+//           values (Eq. 5, read as the statistic the text names): two
+//           bitonic sorts of up to 4096 doubles in LDS.
+//   score   one thread per (trial, cluster), the mapping of Alg. 1: the trial
+//           draws its seed pair from Philox4x32-10 exactly as the
+//           velocity-profile kernels do, fits the line through the two
+//           normalised seeds, and counts the points whose perpendicular
+//           distance (aa x + bb y + cc over sqrt(aa^2 + bb^2)) is at most the
+//           threshold; the block's best (count, lowest index) key is merged per
+//           cluster with a 64-bit atomic maximum.
+//   refit   one workgroup: re-classifies every point under the kept line,
+//           writes the inlier mask, and solves the normal equations of the
+//           velocity profile on the inliers; heading = atan2(vy, vx).
+//
+// Everything is FP64 and evaluated exactly as written (no contraction), so
+// counts, masks and thresholds are the same bits as a plain FP64 evaluation of
+// the same expressions.
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "rv.h"
+#include "rv_device.h"
+#include "rv_internal.h"
+
+#pragma clang fp contract(off)
+
+using rv_internal::fail;
+using rv_internal::g_error;
+using rv_internal::keep_timed_call;
+using rv_internal::take_timed_call;
+using rv_internal::TimedCall;
+
+namespace {
+
+constexpr int kPaperBlock = 256;
+constexpr int kPaperWaves = kPaperBlock / kWave;
+constexpr double kPaperMinSeparation = RV_MIN_SEED_SEPARATION;
+
+// Normalised coordinate of one value: (a - lo) / span, 0 for a zero span.
+__device__ __forceinline__ double unit_coord(float a, double lo, double span) {
+    return span > 0.0 ? ((double)a - lo) / span : 0.0;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Ascending bitonic sort of s[0, P) (P a power of two, <= RV_PAPER_MAX_POINTS)
+// by the whole workgroup; every loop bound is uniform.
+__device__ void bitonic_sort(double *s, int P) {
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P / 2; i += kPaperBlock) {
+                const int lo = (i / stride) * 2 * stride + (i % stride);
+                const int hi = lo + stride;
+                const bool ascending = (lo & size) == 0;
+                const double a = s[lo], b = s[hi];
+                if ((a > b) == ascending) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Median of the m smallest entries of a sorted array (mean of the two middle
+// values for an even m); m >= 1.
+__device__ __forceinline__ double sorted_median(const double *s, int m) {
+    return (m & 1) ? s[m / 2] : (s[m / 2 - 1] + s[m / 2]) / 2.0;
+}
+
+// Spans of a cluster with 2 <= n <= RV_PAPER_MAX_POINTS points, the only ones
+// the score and refit kernels work on.
+__device__ __forceinline__ bool paper_cluster(const Span &sp) {
+    return sp.ok && sp.n >= 2 && sp.n <= RV_PAPER_MAX_POINTS;
+}
+
+__global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd,
+    const int32_t *__restrict__ off, int64_t n_points, double2 *__restrict__ xy,
+    double *__restrict__ thresh, unsigned long long *__restrict__ best_key) {
+    __shared__ double s_sort[RV_PAPER_MAX_POINTS];
+    __shared__ double s_red[4][kPaperWaves];
+    __shared__ int s_cnt[kPaperWaves];
+    const int64_t k = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const Span sp = cluster_span(off, k, n_points);
+    if (tid == 0) {
+        best_key[k] = 0;
+        thresh[k] = __builtin_nan("");
+    }
+    if (!paper_cluster(sp)) return;
+    const int n = (int)sp.n;
+    const float *t = theta + sp.lo, *v = vd + sp.lo;
+
+    double tmin = __builtin_inf(), tmax = -__builtin_inf();
+    double vmin = __builtin_inf(), vmax = -__builtin_inf();
+    int m_ok = 0;
+    for (int p = tid; p < n; p += kPaperBlock) {
+        if (!(isfinite(t[p]) && isfinite(v[p]))) continue;
+        tmin = fmin(tmin, (double)t[p]);
+        tmax = fmax(tmax, (double)t[p]);
+        vmin = fmin(vmin, (double)v[p]);
+        vmax = fmax(vmax, (double)v[p]);
+        m_ok += 1;
+    }
+    tmin = wave_min(tmin);
+    tmax = wave_max(tmax);
+    vmin = wave_min(vmin);
+    vmax = wave_max(vmax);
+    m_ok = wave_sum_i(m_ok);
+    if (lane == 0) {
+        s_red[0][wave] = tmin;
+        s_red[1][wave] = tmax;
+        s_red[2][wave] = vmin;
+        s_red[3][wave] = vmax;
+        s_cnt[wave] = m_ok;
+    }
+    __syncthreads();
+    tmin = s_red[0][0];
+    tmax = s_red[1][0];
+    vmin = s_red[2][0];
+    vmax = s_red[3][0];
+    m_ok = s_cnt[0];
+    for (int w = 1; w < kPaperWaves; ++w) {
+        tmin = fmin(tmin, s_red[0][w]);
+        tmax = fmax(tmax, s_red[1][w]);
+        vmin = fmin(vmin, s_red[2][w]);
+        vmax = fmax(vmax, s_red[3][w]);
+        m_ok += s_cnt[w];
+    }
+    const double tspan = tmax - tmin, vspan = vmax - vmin;
+
+    // Normalised coordinates (x = NaN marks a point that takes no part), and
+    // the finite y values, padded with +inf to a power of two, for the median.
+    int P = 2;
+    while (P < n) P <<= 1;
+    for (int p = tid; p < P; p += kPaperBlock) {
+        double y = __builtin_inf();
+        if (p < n) {
+            const bool ok = isfinite(t[p]) && isfinite(v[p]);
+            const double x = ok ? unit_coord(t[p], tmin, tspan) : __builtin_nan("");
+            y = ok ? unit_coord(v[p], vmin, vspan) : __builtin_inf();
+            xy[sp.lo + p] = make_double2(x, ok ? y : __builtin_nan(""));
+        }
+        s_sort[p] = y;
+    }
+    __syncthreads();
+    if (m_ok == 0) return;
+    bitonic_sort(s_sort, P);
+    const double med = sorted_median(s_sort, m_ok);
+    __syncthreads();
+    for (int p = tid; p < P; p += kPaperBlock) {
+        double d = __builtin_inf();
+        if (p < n && isfinite(t[p]) && isfinite(v[p])) d = fabs(unit_coord(v[p], vmin, vspan) - med);
+        s_sort[p] = d;
+    }
+    __syncthreads();
+    bitonic_sort(s_sort, P);
+    if (tid == 0) thresh[k] = sorted_median(s_sort, m_ok);
+}
+
+// Line of a trial through its normalised seeds (Alg. 1: slope and intercept)
+// and the denominator of its distance.
+struct Line {
+    double m, c, distd;
+    bool valid;
+};
+
+__device__ __forceinline__ Line trial_line(const float *__restrict__ t, const double2 *__restrict__ xy,
+                                           int n, uint32_t h, uint32_t k, uint32_t key0,
+                                           uint32_t key1) {
+    const uint4 u = philox4x32_10(make_uint4(h, k, 0u, 0u), key0, key1);
+    uint32_t i, j;
+    seed_pair(u.x, u.y, (uint32_t)n, i, j);
+    const double2 a = xy[i], b = xy[j];
+    Line L;
+    L.valid = !__builtin_isnan(a.x) && !__builtin_isnan(b.x) &&
+              fabs((double)t[j] - (double)t[i]) >= kPaperMinSeparation;
+    L.m = L.c = L.distd = 0.0;
+    if (!L.valid) return L;
+    L.m = (b.y - a.y) / (b.x - a.x);
+    L.c = a.y - L.m * a.x;
+    const double aa = -L.m, bb = 1.0;
+    L.distd = sqrt(aa * aa + bb * bb);
+    return L;
+}
+
+// Alg. 1's inlier test of one point against a valid line.
+__device__ __forceinline__ bool within(const Line &L, double2 p, double th) {
+    const double aa = -L.m, bb = 1.0, cc = -L.c;
+    const double distn = (aa * p.x + bb * p.y) + cc;
+    return fabs(distn / L.distd) <= th;
+}
+
+// Block = (cluster, 256 trials); thread = one trial (Alg. 1's thread).
+__global__ __launch_bounds__(kPaperBlock) void paper_score_kernel(
+    const float *__restrict__ theta, const int32_t *__restrict__ off, int64_t n_points,
+    int32_t n_hyp, int32_t blocks_per_cluster, uint32_t key0, uint32_t key1,
+    const double2 *__restrict__ xy, const double *__restrict__ thresh,
+    unsigned long long *__restrict__ best_key, int32_t *__restrict__ hyp_counts) {
+    __shared__ unsigned long long s_key[kPaperWaves];
+    const int64_t k = blockIdx.x / blocks_per_cluster;
+    const int b = (int)(blockIdx.x % blocks_per_cluster);
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const int64_t h = (int64_t)b * kPaperBlock + tid;
+    const Span sp = cluster_span(off, k, n_points);
+    if (!paper_cluster(sp)) {
+        if (hyp_counts != nullptr && h < n_hyp) hyp_counts[k * n_hyp + h] = 0;
+        return;
+    }
+    const int n = (int)sp.n;
+    const double2 *pts = xy + sp.lo;
+    const double th = thresh[k];
+    unsigned long long key = 0;
+    if (h < n_hyp) {
+        const Line L = trial_line(theta + sp.lo, pts, n, (uint32_t)h, (uint32_t)k, key0, key1);
+        int count = 0;
+        if (L.valid) {
+            for (int p = 0; p < n; ++p) {
+                const double2 q = pts[p];
+                if (!__builtin_isnan(q.x) && within(L, q, th)) count += 1;
+            }
+            key = ((unsigned long long)count << 32) | (0xFFFFFFFFull - (uint32_t)h);
+        }
+        if (hyp_counts != nullptr) hyp_counts[k * n_hyp + h] = count;
+    }
+    key = wave_max_u64(key);
+    if (lane == 0) s_key[wave] = key;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kPaperWaves; ++w) key = s_key[w] > key ? s_key[w] : key;
+        if (key != 0) atomicMax(&best_key[k], key);
+    }
+}
+
+struct PaperOutputs {
+    float *vx, *vy, *heading;
+    int32_t *n_inliers;
+    uint8_t *status;
+    int32_t *best;
+    uint32_t *bits;
+};
+
+__device__ __forceinline__ void paper_failed(const PaperOutputs &o, int64_t k, uint8_t st) {
+    const float qnan = __builtin_nanf("");
+    o.vx[k] = qnan;
+    o.vy[k] = qnan;
+    o.heading[k] = qnan;
+    o.n_inliers[k] = 0;
+    o.status[k] = st;
+    if (o.best) o.best[k] = -1;
+}
+
+__global__ __launch_bounds__(kPaperBlock) void paper_refit_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd, const int32_t *__restrict__ off,
+    int64_t n_points, uint32_t key0, uint32_t key1, const double2 *__restrict__ xy,
+    const double *__restrict__ thresh, const unsigned long long *__restrict__ best_key,
+    PaperOutputs o) {
+    __shared__ double s_sum[kPaperWaves][5];
+    __shared__ int s_cnt[kPaperWaves];
+    const int64_t k = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+    const Span sp = cluster_span(off, k, n_points);
+    if (!sp.ok || sp.n < 2 || sp.n > RV_PAPER_MAX_POINTS) {
+        if (tid == 0)
+            paper_failed(o, k, !sp.ok ? RV_CLUSTER_BAD_OFFSETS
+                                      : (sp.n < 2 ? RV_CLUSTER_TOO_FEW_POINTS : RV_CLUSTER_TOO_LARGE));
+        return;
+    }
+    const unsigned long long best = best_key[k];
+    if (best == 0) {
+        if (tid == 0) paper_failed(o, k, RV_CLUSTER_ALL_DEGENERATE);
+        return;
+    }
+    const int n = (int)sp.n;
+    const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+    const double2 *pts = xy + sp.lo;
+    const Line L = trial_line(theta + sp.lo, pts, n, hbest, (uint32_t)k, key0, key1);
+    const double th = thresh[k];
+    const int64_t end = sp.lo + sp.n;
+    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
+    int n_in = 0;
+    // 64-aligned global blocks of points, so one wave ballot covers two mask words.
+    for (int64_t p0 = (sp.lo & ~(int64_t)(kWave - 1)) + (int64_t)wave * kWave; p0 < end;
+         p0 += kPaperBlock) {
+        const int64_t p = p0 + lane;
+        bool inlier = false;
+        if (p >= sp.lo && p < end) {
+            const double2 q = xy[p];
+            if (!__builtin_isnan(q.x) && within(L, q, th)) {
+                inlier = true;
+                n_in += 1;
+                double s, c;
+                sincos((double)theta[p], &s, &c);
+                const double dv = vd[p];
+                scc += c * c;
+                scs += c * s;
+                sss += s * s;
+                scv += c * dv;
+                ssv += s * dv;
+            }
+        }
+        if (o.bits != nullptr) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(inlier);
+            if (lane == 0) {
+                const uint32_t w0 = (uint32_t)m, w1 = (uint32_t)(m >> 32);
+                if (w0) atomicOr(&o.bits[p0 >> 5], w0);
+                if (w1) atomicOr(&o.bits[(p0 >> 5) + 1], w1);
+            }
+        }
+    }
+    scc = wave_sum(scc);
+    scs = wave_sum(scs);
+    sss = wave_sum(sss);
+    scv = wave_sum(scv);
+    ssv = wave_sum(ssv);
+    n_in = wave_sum_i(n_in);
+    if (lane == 0) {
+        s_sum[wave][0] = scc;
+        s_sum[wave][1] = scs;
+        s_sum[wave][2] = sss;
+        s_sum[wave][3] = scv;
+        s_sum[wave][4] = ssv;
+        s_cnt[wave] = n_in;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    scc = s_sum[0][0];
+    scs = s_sum[0][1];
+    sss = s_sum[0][2];
+    scv = s_sum[0][3];
+    ssv = s_sum[0][4];
+    n_in = s_cnt[0];
+    for (int w = 1; w < kPaperWaves; ++w) {
+        scc += s_sum[w][0];
+        scs += s_sum[w][1];
+        sss += s_sum[w][2];
+        scv += s_sum[w][3];
+        ssv += s_sum[w][4];
+        n_in += s_cnt[w];
+    }
+    o.n_inliers[k] = n_in;
+    if (o.best) o.best[k] = (int32_t)hbest;
+    const double det = scc * sss - scs * scs;
+    if (n_in < 2 || !(det > 0.0)) {
+        const float qnan = __builtin_nanf("");
+        o.vx[k] = qnan;
+        o.vy[k] = qnan;
+        o.heading[k] = qnan;
+        o.status[k] = RV_CLUSTER_SINGULAR_REFIT;
+        return;
+    }
+    const double fvx = (sss * scv - scs * ssv) / det;
+    const double fvy = (scc * ssv - scs * scv) / det;
+    o.vx[k] = (float)fvx;
+    o.vy[k] = (float)fvy;
+    o.heading[k] = (float)atan2(fvy, fvx);
+    o.status[k] = RV_CLUSTER_OK;
+}
+
+__global__ __launch_bounds__(kPaperBlock) void paper_clear_bits_kernel(uint32_t *__restrict__ bits,
+                                                                      int64_t n_words) {
+    const int64_t i = (int64_t)blockIdx.x * kPaperBlock + threadIdx.x;
+    if (i < n_words) bits[i] = 0u;
+}
+
+constexpr size_t kPaperAlign = 256;
+
+size_t paper_align(size_t x) { return (x + kPaperAlign - 1) / kPaperAlign * kPaperAlign; }
+
+struct PaperLayout {
+    size_t xy, thresh, best_key, total;
+};
+
+PaperLayout paper_layout(int64_t n_clusters, int64_t n_points) {
+    PaperLayout L;
+    size_t at = 0;
+    L.xy = at; at = paper_align(at + (size_t)n_points * sizeof(double2));
+    L.thresh = at; at = paper_align(at + (size_t)n_clusters * sizeof(double));
+    L.best_key = at; at = paper_align(at + (size_t)n_clusters * sizeof(unsigned long long));
+    L.total = at;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rv_paper_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t n_hyp) {
+    if (n_clusters < 0 || n_points < 0 || n_hyp < 0) return 0;
+    return paper_layout(n_clusters, n_points).total;
+}
+
+int rv_estimate_velocity_paper(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                               int64_t n_clusters, int64_t n_points, int32_t n_hyp, uint64_t seed,
+                               float *vx, float *vy, float *heading, int32_t *n_inliers,
+                               uint8_t *status, double *thresh, uint32_t *inlier_bits,
+                               int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+    g_error[0] = '\0';
+    if (n_hyp < 1 || n_hyp > RV_MAX_HYP)
+        return fail(RV_ERR_INVALID_ARG, "n_hyp must be in [1, %d]", RV_MAX_HYP);
+    if (n_clusters < 0 || n_clusters > INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "n_clusters must be in [0, 2^31 - 1]");
+    if (n_points < 0 || n_points > INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "n_points must be in [0, 2^31 - 1]");
+    if (cluster_offsets == nullptr) return fail(RV_ERR_INVALID_ARG, "cluster_offsets is NULL");
+    if (n_points > 0 && (theta == nullptr || vd == nullptr))
+        return fail(RV_ERR_INVALID_ARG, "theta or vd is NULL");
+    if (n_clusters > 0 && (vx == nullptr || vy == nullptr || heading == nullptr ||
+                           n_inliers == nullptr || status == nullptr))
+        return fail(RV_ERR_INVALID_ARG, "a required output is NULL");
+    const PaperLayout L = paper_layout(n_clusters, n_points);
+    if (workspace == nullptr || workspace_bytes < L.total)
+        return fail(RV_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
+                    workspace == nullptr ? (size_t)0 : workspace_bytes);
+    if (((uintptr_t)workspace % kPaperAlign) != 0)
+        return fail(RV_ERR_WORKSPACE, "workspace must be %zu-byte aligned", kPaperAlign);
+    if (n_clusters == 0) return RV_OK;
+    const int64_t bpc = ((int64_t)n_hyp + kPaperBlock - 1) / kPaperBlock;
+    if (n_clusters * bpc > INT32_MAX) return fail(RV_ERR_INVALID_ARG, "n_clusters * n_hyp too large");
+    char *ws = (char *)workspace;
+    double2 *xy = (double2 *)(ws + L.xy);
+    double *th = thresh != nullptr ? thresh : (double *)(ws + L.thresh);
+    unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
+    const uint32_t key0 = (uint32_t)(seed & 0xFFFFFFFFu), key1 = (uint32_t)(seed >> 32);
+    hipStream_t st = (hipStream_t)stream;
+    // Stage events (rv_stage_timing): stats and mask clearing, scoring, refit.
+    TimedCall tc;
+    const bool timed = take_timed_call(tc);
+    if (timed) (void)hipEventRecord(tc.ev[0], st);
+    if (inlier_bits != nullptr) {
+        const int64_t n_words = (n_points + 31) / 32;
+        if (n_words > 0)
+            hipLaunchKernelGGL(paper_clear_bits_kernel,
+                               dim3((unsigned)((n_words + kPaperBlock - 1) / kPaperBlock)),
+                               dim3(kPaperBlock), 0, st, inlier_bits, n_words);
+    }
+    hipLaunchKernelGGL(paper_stats_kernel, dim3((unsigned)n_clusters), dim3(kPaperBlock), 0, st,
+                       theta, vd, cluster_offsets, n_points, xy, th, best_key);
+    if (timed) (void)hipEventRecord(tc.ev[1], st);
+    hipLaunchKernelGGL(paper_score_kernel, dim3((unsigned)(n_clusters * bpc)), dim3(kPaperBlock), 0,
+                       st, theta, cluster_offsets, n_points, n_hyp, (int32_t)bpc, key0, key1,
+                       (const double2 *)xy, (const double *)th, best_key, hyp_counts);
+    if (timed) (void)hipEventRecord(tc.ev[2], st);
+    PaperOutputs o;
+    o.vx = vx;
+    o.vy = vy;
+    o.heading = heading;
+    o.n_inliers = n_inliers;
+    o.status = status;
+    o.best = best_hyp;
+    o.bits = inlier_bits;
+    hipLaunchKernelGGL(paper_refit_kernel, dim3((unsigned)n_clusters), dim3(kPaperBlock), 0, st,
+                       theta, vd, cluster_offsets, n_points, key0, key1, (const double2 *)xy,
+                       (const double *)th, (const unsigned long long *)best_key, o);
+    if (timed) {
+        (void)hipEventRecord(tc.ev[3], st);
+        keep_timed_call(tc);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(RV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return RV_OK;
+}
+
+}  // extern "C"

@@ -86,7 +86,7 @@ WORKLOADS = {
 }
 # Data seed of each workload and the per-frame hypothesis seed convention:
 # hypothesis seed = (workload number << 32) | frame index.
-WORKLOAD_NUMBER = {"small": 1, "dense": 2, "batched": 3, "served": 4}
+WORKLOAD_NUMBER = {"small": 1, "dense": 2, "batched": 3, "served": 4, "paper": 5}
 
 
 @dataclasses.dataclass(frozen=True)
@@ -252,3 +252,15 @@ def make_batch(spec: BatchSpec, seed: int, workload: str = "batched", n_frames: 
 def make_batch_workload(name: str, n_frames: int | None = None) -> tuple[Batch, int, float]:
     spec, n_hyp, tau = BATCH_WORKLOADS[name]
     return make_batch(spec, WORKLOAD_NUMBER[name], workload=name, n_frames=n_frames), n_hyp, tau
+
+
+# The paper's timing tables (Table I: RANSAC, Table II: least squares) sweep
+# {8, 16, 32, 64} clusters x {100, 150} points per cluster.
+TABLE_SHAPES = [(c, p) for c in (8, 16, 32, 64) for p in (100, 150)]
+
+
+def table_frame(n_clusters: int, points: int, seed: int | None = None) -> Frame:
+    """A frame of the Table I/II shape: fixed cluster size, 20 % uniform outliers."""
+    spec = FrameSpec(n_clusters=n_clusters, size_kind="fixed", size_lo=points, size_hi=points,
+                     p_uniform=0.20)
+    return make_frame(spec, (5 << 20) + n_clusters * 1000 + points if seed is None else seed)

@@ -189,3 +189,24 @@ def test_server_host_checks(lib):
     assert lib.rv_server_result(None, 1, None, None, None, None, None, None, None) == -1
     assert lib.rv_server_stats(None, None) == -1
     lib.rv_server_destroy(None)
+
+
+def test_paper_variant_host_checks(lib):
+    from paper_2012_12618_amd import binding
+
+    assert binding.rv_paper_workspace_bytes(10, 1000, 64) >= 16 * 1000 + 16 * 10
+    fake = ctypes.c_void_p(4096)
+
+    def call(**kw):
+        a = dict(theta=fake, vd=fake, off=fake, K=2, N=10, H=16, out=fake, ws=None, ws_bytes=0)
+        a.update(kw)
+        return lib.rv_estimate_velocity_paper(a["theta"], a["vd"], a["off"], a["K"], a["N"], a["H"],
+                                              1, a["out"], a["out"], a["out"], a["out"], a["out"],
+                                              None, None, None, None, a["ws"], a["ws_bytes"], None)
+
+    for kw, code, word in ((dict(H=0), -1, "n_hyp"), (dict(off=None), -1, "cluster_offsets"),
+                           (dict(theta=None), -1, "theta"), (dict(out=None), -1, "output"),
+                           (dict(), -2, "workspace")):
+        assert call(**kw) == code, kw
+        assert word in lib.rv_last_error().decode()
+    assert call(K=0, N=0, ws=fake, ws_bytes=1 << 20) == 0
