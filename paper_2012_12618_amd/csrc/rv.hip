@@ -17,7 +17,8 @@
 //           and inlier count).  The best (count, lowest index) key of the block
 //           is merged per cluster with a 64-bit atomic maximum (Sec. 3.1: the
 //           trial with the most inliers is kept).
-//   refit   one workgroup per cluster: FP64 re-classification under the kept
+//   refit   one wave per cluster, or the whole workgroup for clusters of
+//           1024 points or more: FP64 re-classification under the kept
 //           hypothesis, FP64 normal-equation sums in a fixed reduction tree,
 //           2x2 solve (Sec. 3.2, Eq. 7, Alg. 2) and atan2 heading (Eq. 8).
 //
@@ -32,6 +33,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -85,6 +87,8 @@ namespace {
 
 constexpr int kScoreBlock = 256;        // score: 4 waves x 64 hypotheses, one per thread
 constexpr int kRefitBlock = 256;
+constexpr int kRefitWaves = kRefitBlock / 64;  // clusters per refit workgroup
+constexpr int kRefitBigClass = 41;             // size class of 1024 points: a workgroup each
 constexpr int kXcds = 8;                // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int kPrepBlock = 256;
 constexpr int kRowsMax = 16;            // rows of 64 points held in registers per pass
@@ -154,7 +158,8 @@ __device__ __forceinline__ int size_class(int64_t n) {
 // the longest workgroups start first (longest-processing-time-first).  The
 // order inside a class depends on atomics; it only affects scheduling.
 __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
-                           int64_t n_points, int32_t *__restrict__ order) {
+                           int64_t n_points, int32_t *__restrict__ order,
+                           int64_t *__restrict__ n_big) {
     __shared__ uint32_t count[kSizeClasses];
     __shared__ uint32_t start[kSizeClasses];
     for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) count[c] = 0;
@@ -167,6 +172,7 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
         for (int c = kSizeClasses - 1; c >= 0; --c) {
             start[c] = at;
             at += count[c];
+            if (c == kRefitBigClass) *n_big = at;  // clusters refit by a whole workgroup
         }
     }
     __syncthreads();
@@ -183,9 +189,10 @@ __global__ __launch_bounds__(kPrepBlock) void prep_kernel(
     float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
     uint32_t *__restrict__ bits,
     int64_t n_words, const int32_t *__restrict__ off, int64_t n_clusters,
-    int32_t *__restrict__ order, unsigned long long *__restrict__ best_key) {
+    int32_t *__restrict__ order, int64_t *__restrict__ n_big,
+    unsigned long long *__restrict__ best_key) {
     if (blockIdx.x == gridDim.x - 1) {
-        if (order != nullptr) plan_order(off, n_clusters, n_points, order);
+        if (order != nullptr) plan_order(off, n_clusters, n_points, order, n_big);
         return;
     }
     const int64_t p = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
@@ -486,6 +493,91 @@ __device__ __forceinline__ void refit_block(Span sp, ClusterId id, unsigned long
     o.status[k] = RV_CLUSTER_OK;
 }
 
+// Refit of one cluster by one wave: the kept hypothesis (from its best key),
+// FP64 re-classification of every point under it, least-squares refit on its
+// inliers (Sec. 3.2, Eq. 7, Alg. 2: normal equations A^T A v = A^T v_d, summed
+// per lane over the cluster's 64-point blocks and reduced across the wave in a
+// fixed tree) and heading atan2(vy, vx) (Eq. 8).  One wave per cluster keeps
+// small clusters from idling a whole workgroup and needs no barrier.
+__device__ __forceinline__ void refit_wave(Span sp, ClusterId id, unsigned long long best,
+                                           const Points &pts, float tau, const Outputs &o) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t k = id.out;
+    if (!sp.ok || sp.n < 2) {
+        if (lane == 0) write_failed(o, k, sp.ok ? RV_CLUSTER_TOO_FEW_POINTS : RV_CLUSTER_BAD_OFFSETS);
+        return;
+    }
+    if (best == 0) {
+        if (lane == 0) write_failed(o, k, RV_CLUSTER_ALL_DEGENERATE);
+        return;
+    }
+    const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+    const Hypothesis hy = make_hypothesis(pts, sp, hbest, id.local, id.key0, id.key1);
+    const double dtau = tau;
+
+    // 64-aligned global blocks of points, so one ballot maps onto two words of
+    // the frame-wide bitmask.
+    const int64_t end = sp.lo + sp.n;
+    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
+    int n_in = 0, n_near = 0;
+    for (int64_t p0 = sp.lo & ~(int64_t)(kWave - 1); p0 < end; p0 += kWave) {
+        const int64_t p = p0 + lane;
+        bool inlier = false;
+        if (p >= sp.lo && p < end) {
+            const float v = pts.v32[p];  // +inf marks a non-finite point
+            if (isfinite(v)) {
+                const double2 cs = pts.cs64[p];
+                const double c = cs.x, s = cs.y, dv = v;
+                const double res = fabs(dv - hy.vx * c - hy.vy * s);
+                n_near += fabs(res - dtau) <= RV_NEAR_TAU_WINDOW ? 1 : 0;
+                if (res < dtau) {
+                    inlier = true;
+                    n_in += 1;
+                    scc += c * c;
+                    scs += c * s;
+                    sss += s * s;
+                    scv += c * dv;
+                    ssv += s * dv;
+                }
+            }
+        }
+        if (o.bits != nullptr) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(inlier);
+            if (lane == 0) {
+                const uint32_t w0 = (uint32_t)m, w1 = (uint32_t)(m >> 32);
+                if (w0) atomicOr(&o.bits[p0 >> 5], w0);
+                if (w1) atomicOr(&o.bits[(p0 >> 5) + 1], w1);
+            }
+        }
+    }
+    scc = wave_sum(scc);
+    scs = wave_sum(scs);
+    sss = wave_sum(sss);
+    scv = wave_sum(scv);
+    ssv = wave_sum(ssv);
+    n_in = wave_sum_i(n_in);
+    n_near = wave_sum_i(n_near);
+    if (lane != 0) return;
+    o.n_inliers[k] = n_in;
+    if (o.n_near) o.n_near[k] = n_near;
+    if (o.best) o.best[k] = (int32_t)hbest;
+    const double det = scc * sss - scs * scs;
+    if (n_in < 2 || !(det > 0.0)) {
+        const float qnan = __builtin_nanf("");
+        o.vx[k] = qnan;
+        o.vy[k] = qnan;
+        o.heading[k] = qnan;
+        o.status[k] = RV_CLUSTER_SINGULAR_REFIT;
+        return;
+    }
+    const double fvx = (sss * scv - scs * ssv) / det;
+    const double fvy = (scc * ssv - scs * scv) / det;
+    o.vx[k] = (float)fvx;
+    o.vy[k] = (float)fvy;
+    o.heading[k] = (float)atan2(fvy, fvx);
+    o.status[k] = RV_CLUSTER_OK;
+}
+
 // ---- single frame ---------------------------------------------------------
 
 // Work item = (cluster, block of 256 hypotheses).  Block i takes the item that
@@ -515,20 +607,57 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
                        s_key, best_key, hyp_counts);
 }
 
-// One workgroup per cluster, clusters in the planned order.
+// Refit of a frame's or batch's clusters over their planned (largest-first)
+// positions, in one launch: workgroups [0, n_big) take the first n_big
+// clusters (size class >= kRefitBigClass, i.e. >= 1024 points), one each with
+// all four waves (refit_block); the following workgroups take the other
+// clusters four at a time, one per wave (refit_wave).  n_big is counted on the
+// device by the ordering pass; without an order (n_big == nullptr) every
+// cluster gets a workgroup.  The grid is an upper bound (one workgroup per
+// cluster); surplus workgroups exit at once.
+template <typename ClusterAt>
+__device__ __forceinline__ void refit_planned(int64_t n_clusters, const int64_t *n_big,
+                                              const ClusterAt &at, const Points &pts, float tau,
+                                              const Outputs &o, double (*s_sum)[5],
+                                              int (*s_cnt)[2]) {
+    const int64_t b = blockIdx.x;
+    const int64_t big = n_big != nullptr ? *n_big : n_clusters;
+    if (b < big) {
+        refit_block(at.span(b), at.id(b), at.best(b), pts, tau, o, s_sum, s_cnt);
+        return;
+    }
+    const int64_t j = big + (b - big) * kRefitWaves + threadIdx.x / kWave;
+    if (j >= n_clusters) return;
+    refit_wave(at.span(j), at.id(j), at.best(j), pts, tau, o);
+}
+
+// Cluster at planned position j of a single frame.
+struct FrameClusterAt {
+    const int32_t *off, *order;
+    int64_t n_points;
+    uint32_t key0, key1;
+    const unsigned long long *best_key;
+    __device__ int64_t index(int64_t j) const { return order != nullptr ? order[j] : j; }
+    __device__ Span span(int64_t j) const { return cluster_span(off, index(j), n_points); }
+    __device__ unsigned long long best(int64_t j) const { return best_key[index(j)]; }
+    __device__ ClusterId id(int64_t j) const {
+        ClusterId c;
+        c.out = index(j);
+        c.local = (uint32_t)c.out;
+        c.key0 = key0;
+        c.key1 = key1;
+        return c;
+    }
+};
+
 __global__ __launch_bounds__(kRefitBlock) void refit_kernel(
-    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_points,
-    uint32_t key0, uint32_t key1, Points pts, const unsigned long long *__restrict__ best_key,
-    float tau, Outputs o) {
+    const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
+    const int64_t *__restrict__ n_big, int64_t n_points, uint32_t key0, uint32_t key1, Points pts,
+    const unsigned long long *__restrict__ best_key, float tau, Outputs o) {
     __shared__ double s_sum[kRefitBlock / kWave][5];
     __shared__ int s_cnt[kRefitBlock / kWave][2];
-    const int64_t k = order != nullptr ? order[blockIdx.x] : (int64_t)blockIdx.x;
-    ClusterId id;
-    id.out = k;
-    id.local = (uint32_t)k;
-    id.key0 = key0;
-    id.key1 = key1;
-    refit_block(cluster_span(off, k, n_points), id, best_key[k], pts, tau, o, s_sum, s_cnt);
+    const FrameClusterAt at = {off, order, n_points, key0, key1, best_key};
+    refit_planned(n_clusters, n_big, at, pts, tau, o, s_sum, s_cnt);
 }
 
 // ---- many frames in one launch sequence ----------------------------------
@@ -647,13 +776,15 @@ __global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(
 }
 
 // Start of each size class in the dispatch order (largest class first).
-__global__ __launch_bounds__(64) void batch_scan_kernel(uint32_t *__restrict__ hist) {
+__global__ __launch_bounds__(64) void batch_scan_kernel(uint32_t *__restrict__ hist,
+                                                        int64_t *__restrict__ n_big) {
     if (threadIdx.x != 0) return;
     uint32_t at = 0;
     for (int c = kSizeClasses - 1; c >= 0; --c) {
         const uint32_t n = hist[c];
         hist[c] = at;
         at += n;
+        if (c == kRefitBigClass) *n_big = at;  // clusters refit by a whole workgroup
     }
 }
 
@@ -736,13 +867,22 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))
     }
 }
 
+// Cluster at dispatch position j of a batch (its descriptor).
+struct BatchClusterAt {
+    const ItemDesc *desc;
+    const unsigned long long *best_key;
+    __device__ Span span(int64_t j) const { return desc_span(desc[j]); }
+    __device__ ClusterId id(int64_t j) const { return desc_id(desc[j]); }
+    __device__ unsigned long long best(int64_t j) const { return best_key[desc[j].out]; }
+};
+
 __global__ __launch_bounds__(kRefitBlock) void batch_refit_kernel(
-    const ItemDesc *__restrict__ desc, Points pts, const unsigned long long *__restrict__ best_key,
-    float tau, Outputs o) {
+    const ItemDesc *__restrict__ desc, int64_t n_clusters, const int64_t *__restrict__ n_big,
+    Points pts, const unsigned long long *__restrict__ best_key, float tau, Outputs o) {
     __shared__ double s_sum[kRefitBlock / kWave][5];
     __shared__ int s_cnt[kRefitBlock / kWave][2];
-    const ItemDesc d = desc[blockIdx.x];
-    refit_block(desc_span(d), desc_id(d), best_key[d.out], pts, tau, o, s_sum, s_cnt);
+    const BatchClusterAt at = {desc, best_key};
+    refit_planned(n_clusters, n_big, at, pts, tau, o, s_sum, s_cnt);
 }
 
 __global__ __launch_bounds__(kPrepBlock) void philox_kernel(const uint32_t *__restrict__ ctr,
@@ -780,7 +920,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t cs32, v32, cs64, order, best_key, total;
+    size_t cs32, v32, cs64, order, best_key, n_big, total;
 };
 
 Layout make_layout(int64_t n_clusters, int64_t n_points) {
@@ -792,6 +932,7 @@ Layout make_layout(int64_t n_clusters, int64_t n_points) {
     L.cs64 = at; at = align_up(at + np * sizeof(double2));
     L.order = at; at = align_up(at + (size_t)n_clusters * sizeof(int32_t));
     L.best_key = at; at = align_up(at + (size_t)n_clusters * sizeof(unsigned long long));
+    L.n_big = at; at = align_up(at + sizeof(int64_t));
     L.total = at;
     return L;
 }
@@ -800,7 +941,7 @@ Layout make_layout(int64_t n_clusters, int64_t n_points) {
 
 
 struct BatchLayout {
-    size_t cs32, v32, cs64, desc, best_key, hist, queues, total;
+    size_t cs32, v32, cs64, desc, best_key, hist, queues, n_big, total;
 };
 
 BatchLayout make_batch_layout(int64_t n_clusters, int64_t n_points) {
@@ -814,6 +955,7 @@ BatchLayout make_batch_layout(int64_t n_clusters, int64_t n_points) {
     L.best_key = at; at = align_up(at + nc * sizeof(unsigned long long));
     L.hist = at; at = align_up(at + kSizeClasses * sizeof(uint32_t));
     L.queues = at; at = align_up(at + kXcds * kQueueStride * sizeof(unsigned long long));
+    L.n_big = at; at = align_up(at + sizeof(int64_t));
     L.total = at;
     return L;
 }
@@ -867,11 +1009,39 @@ int64_t batch_blocks_per_cluster(const BatchArgs &a) {
     return ((int64_t)a.n_hyp + kScoreBlock - 1) / kScoreBlock;
 }
 
+// Compute units of the current device, queried once per device (a launch that
+// is being captured into a graph only reads the cache, filled by the caller's
+// earlier call).
+int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int cus = cache[dev].load(std::memory_order_relaxed);
+    if (cus > 0) return cus;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cache[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
+
+// The refit kernel over planned positions; n_big (device, nullable) is the
+// ordering pass's count of big clusters.
+void launch_refit(bool batch, const int32_t *off, const int32_t *order, const ItemDesc *desc,
+                  int64_t n_clusters, const int64_t *n_big, int64_t n_points, uint32_t key0,
+                  uint32_t key1, const Points &pts, const unsigned long long *best_key, float tau,
+                  const Outputs &o, hipStream_t st) {
+    if (batch)
+        hipLaunchKernelGGL(batch_refit_kernel, dim3((unsigned)n_clusters), dim3(kRefitBlock), 0, st,
+                           desc, n_clusters, n_big, pts, best_key, tau, o);
+    else
+        hipLaunchKernelGGL(refit_kernel, dim3((unsigned)n_clusters), dim3(kRefitBlock), 0, st, off,
+                           order, n_clusters, n_big, n_points, key0, key1, pts, best_key, tau, o);
+}
+
 // Persistent grid of the batched scoring kernel on the current device.
 int persistent_blocks(int blocks_per_cu, int64_t items, unsigned *grid) {
-    int dev = 0, cus = 0, fit = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+    int fit = 0;
+    const int cus = device_cus();
+    if (cus <= 0 ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_score_kernel, kScoreBlock, 0) !=
             hipSuccess)
         return fail(RV_ERR_HIP, "device query failed");
@@ -896,6 +1066,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
     uint32_t *hist = (uint32_t *)(ws + L.hist);
     unsigned long long *queues = (unsigned long long *)(ws + L.queues);
+    int64_t *n_big = (int64_t *)(ws + L.n_big);
     Points pts;
     pts.cs32 = cs32;
     pts.v32 = v32;
@@ -919,7 +1090,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)((prep_items + kPrepBlock - 1) / kPrepBlock)),
                        dim3(kPrepBlock), 0, st, a.theta, a.vd, a.n_points, cs32, v32, cs64,
                        a.o.bits, n_words, a.off, a.n_clusters, best_key, hist);
-    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(64), 0, st, hist);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(64), 0, st, hist, n_big);
     hipLaunchKernelGGL(batch_scatter_kernel,
                        dim3((unsigned)((a.n_clusters + kPrepBlock - 1) / kPrepBlock)),
                        dim3(kPrepBlock), 0, st, a.off, a.n_clusters, a.n_points, bt, tune, hist, desc);
@@ -928,8 +1099,8 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
                        (const ItemDesc *)desc, a.n_clusters, a.n_hyp, (int32_t)bpc, pts, a.tau,
                        queues, best_key, a.o.hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
-    hipLaunchKernelGGL(batch_refit_kernel, dim3((unsigned)a.n_clusters), dim3(kRefitBlock), 0, st,
-                       (const ItemDesc *)desc, pts, (const unsigned long long *)best_key, a.tau, a.o);
+    launch_refit(true, nullptr, nullptr, (const ItemDesc *)desc, a.n_clusters, n_big, a.n_points,
+                 0, 0, pts, best_key, a.tau, a.o, st);
     if (timed) {
         (void)hipEventRecord(tc.ev[3], st);
         keep_timed_call(tc);
@@ -1029,6 +1200,7 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     pts.cs64 = cs64;
     pts.theta = theta;
     int32_t *order = n_clusters <= kPlanMaxClusters ? (int32_t *)(ws + L.order) : nullptr;
+    int64_t *n_big = (int64_t *)(ws + L.n_big);
     unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
     const uint32_t key0 = (uint32_t)(seed & 0xFFFFFFFFu), key1 = (uint32_t)(seed >> 32);
     const int64_t n_words = inlier_bits != nullptr ? (n_points + 31) / 32 : 0;
@@ -1042,7 +1214,7 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     const int64_t prep_blocks = (prep_items + kPrepBlock - 1) / kPrepBlock + 1;  // + planner
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)prep_blocks), dim3(kPrepBlock), 0, st, theta,
                        vd, n_points, cs32, v32, cs64, inlier_bits, n_words, cluster_offsets,
-                       n_clusters, order, best_key);
+                       n_clusters, order, n_big, best_key);
     if (timed) (void)hipEventRecord(tc.ev[1], st);
     hipLaunchKernelGGL(score_kernel, dim3((unsigned)(clusters_xcd * blocks_per_cluster)),
                        dim3(kScoreBlock), 0, st, cluster_offsets, (const int32_t *)order,
@@ -1059,9 +1231,9 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     o.best = best_hyp;
     o.hyp_counts = hyp_counts;
     o.bits = inlier_bits;
-    hipLaunchKernelGGL(refit_kernel, dim3((unsigned)n_clusters), dim3(kRefitBlock), 0, st,
-                       cluster_offsets, (const int32_t *)order, n_points, key0, key1,
-                       pts, (const unsigned long long *)best_key, tau, o);
+    launch_refit(false, cluster_offsets, order, nullptr, n_clusters,
+                 order != nullptr ? (const int64_t *)n_big : nullptr, n_points, key0, key1, pts,
+                 best_key, tau, o, st);
     if (timed) {
         (void)hipEventRecord(tc.ev[3], st);
         keep_timed_call(tc);
