@@ -170,3 +170,34 @@ def test_autotuned_setting_gives_identical_results(rv):
     b = _run_batch(rv, batch, H, tau, "default")
     for k in KEYS + ("hyp_counts", "inlier_bits"):
         assert np.array_equal(a[k], b[k], equal_nan=k in ("vx", "vy", "heading")), k
+
+
+def test_full_batch_in_bench_configuration(rv, oracle_mod):
+    """The full batched workload (256 frames) as the benchmark runs it (captured
+    graph, no debug outputs): equal bit for bit to an eager debug call, and in
+    parity with the oracle on 12 frames spread over the batch."""
+    batch, H, tau = synth.make_batch_workload("batched")
+    t, v, o, fo, sd = _dev(batch)
+    K, N, F = batch.frame.n_clusters, batch.frame.n_points, batch.n_frames
+    print(f"[gpu] full batch graph F={F} K={K} N={N} H={H}", flush=True)
+    out = rv.allocate_batch_outputs(F, K, N, H, "cuda:0", want_near=True)
+    graph = rv.rv_graph_capture_batch(t, v, o, fo, sd, H, tau, out)
+    try:
+        graph.launch()
+        torch.cuda.synchronize()
+    finally:
+        graph.destroy()
+    g = _run_batch(rv, batch, H, tau, "full-debug")
+    for k in ("vx", "vy", "heading", "n_inliers", "status", "n_near_tau"):
+        assert np.array_equal(out[k].cpu().numpy(), g[k], equal_nan=k in ("vx", "vy", "heading")), k
+    for f in np.linspace(0, F - 1, 12).astype(int):
+        fr = batch.frame_slice(int(f))
+        c0, c1 = int(batch.frame_offsets[f]), int(batch.frame_offsets[f + 1])
+        p0 = int(batch.frame.offsets[c0])
+        sub = {k: g[k][c0:c1] for k in KEYS}
+        sub["hyp_counts"] = g["hyp_counts"][c0 * H:c1 * H]
+        sub["mask"] = g["mask"][p0:p0 + fr.n_points]
+        ref = oracle_mod.estimate_velocity(fr.theta, fr.vd, fr.offsets, H, tau, int(batch.seeds[f]),
+                                           debug=True)
+        parity.report(f"full-batch-frame{f}",
+                      parity.check(fr.theta, fr.vd, fr.offsets, H, tau, int(batch.seeds[f]), sub, ref))

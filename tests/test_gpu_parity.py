@@ -223,3 +223,11 @@ def test_stage_timing_and_errors(rv):
         rv.rv_estimate_velocity(t, v, o, 0, tau, 1)
     assert e.value.code == rv.RV_ERR_INVALID_ARG
     torch.cuda.synchronize()
+
+
+def test_parity_precision_stress_shape(rv, oracle_mod):
+    """Clusters of the precision-stress configuration (65,536 points each, 40 %
+    micro-Doppler band outliers, 4096 hypotheses), every output checked."""
+    spec = synth.FrameSpec(8, "fixed", 65536, 65536, p_uniform=0.0, p_band=0.4)
+    frame = synth.make_frame(spec, seed=505)
+    _parity(oracle_mod, "stress-65536x4096", frame.theta, frame.vd, frame.offsets, 4096, 0.15, 505)
