@@ -17,7 +17,10 @@ point tile.
 
 The tuner times whole batched calls on the caller's own inputs (coordinate
 descent: one bucket at a time, then the grid), keeps the fastest setting per
-coordinate, and can save the table as JSON keyed by device name and n_hyp.
+coordinate, then times the winner and the default alternately and keeps the
+winner only when it is faster by more than ``min_gain`` (timings drift by a
+few per cent over a run).  The table can be saved as JSON keyed by device name
+and n_hyp.
 """
 from __future__ import annotations
 
@@ -70,7 +73,7 @@ def _time_call(fn, reps: int) -> float:
 
 def autotune(theta, vd, offsets, frame_offsets, seeds, n_hyp: int, tau: float, *,
              offsets_host=None, reps: int = 3, rows=ROW_CANDIDATES, grids=GRID_CANDIDATES,
-             log=None) -> tuple[binding.RVTuning, dict]:
+             min_gain: float = 0.01, log=None) -> tuple[binding.RVTuning, dict]:
     """Pick rows_max per bucket and blocks_per_cu for this batch; returns (tuning, report)."""
     n_frames = int(frame_offsets.numel()) - 1
     out = binding.allocate_batch_outputs(n_frames, int(offsets.numel()) - 1, int(theta.numel()),
@@ -108,7 +111,20 @@ def autotune(theta, vd, offsets, frame_offsets, seeds, n_hyp: int, tau: float, *
             log(f"blocks_per_cu {gsz}: {ms:.3f} ms (best {best_ms:.3f})")
         if ms < best_ms:
             best, best_ms = cand, ms
-    return best, {"best": best.to_dict(), "best_ms": best_ms, "trials": trials}
+    # Drift check: the winner and the default, timed alternately; the winner is
+    # kept only if it is faster by more than min_gain.
+    default = binding.rv_tuning_default()
+    a_ms, d_ms = [], []
+    for _ in range(3):
+        a_ms.append(_time_call(lambda: run(best), reps))
+        d_ms.append(_time_call(lambda: run(default), reps))
+    a, d = statistics.median(a_ms), statistics.median(d_ms)
+    kept = a < d * (1.0 - min_gain)
+    if log:
+        log(f"winner {a:.3f} ms vs default {d:.3f} ms: {'kept' if kept else 'default kept'}")
+    if not kept:
+        best, a = default, d
+    return best, {"best": best.to_dict(), "best_ms": a, "default_ms": d, "trials": trials}
 
 
 def table_key(device_name: str, n_hyp: int) -> str:
