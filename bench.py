@@ -281,15 +281,18 @@ def served_bench(args, torch, binding, synth, dev) -> int:
         server = make_server(max_batch, n_streams)
         try:
             print(f"[bench] {form}: warmup", file=sys.stderr, flush=True)
-            serve.run_traffic(server, frames, warm, seed_of, n_hyp, paced=False)
+            serve.run_traffic(server, frames, warm, seed_of, n_hyp, paced=False,
+                              submitters=args.submitters)
             print(f"[bench] {form}: {len(schedule)} paced arrivals over {args.duration} s",
                   file=sys.stderr, flush=True)
-            paced, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=True)
+            paced, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=True,
+                                         submitters=args.submitters)
             print(f"[bench] {form}: same arrivals unpaced", file=sys.stderr, flush=True)
             if form == "served":
                 binding.rv_stage_times()
                 binding.rv_stage_timing(True)
-            sat, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=False)
+            sat, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=False,
+                                       submitters=args.submitters)
             if form == "served":
                 binding.rv_stage_timing(False)
                 out["stages"] = binding.rv_stage_times()
@@ -338,7 +341,8 @@ def served_bench(args, torch, binding, synth, dev) -> int:
                    "duration_s": args.duration, "frames": len(schedule), "n_hyp": n_hyp, "tau": tau,
                    "distinct_frame_contents": n_radars,
                    "value_scope": "frames submitted back to back from host memory, results back "
-                                  "in host memory (copies included)"},
+                                  "in host memory (copies included)",
+                   "submitters": args.submitters},
         "clusters_per_s": sat_s["clusters_per_s"],
         "latency_ms": paced_s["latency_ms"],
         "served_form": brief(paced_s, sat_s),
@@ -477,6 +481,8 @@ def main() -> int:
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: min(16, cpus))")
     ap.add_argument("--frames", type=int, default=0,
                     help="batched workload: number of frames (0: the workload's 256)")
+    ap.add_argument("--submitters", type=int, default=4,
+                    help="served workload: threads submitting frames (radars dealt round-robin)")
     ap.add_argument("--duration", type=float, default=5.0,
                     help="served workload: seconds of simulated arrivals in the timed run")
     ap.add_argument("--host-comparators", action="store_true",

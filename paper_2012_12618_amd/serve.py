@@ -56,7 +56,7 @@ class TrafficReport:
     clusters: int
     evals: int
     wall_s: float                 # first submit to last result
-    latency_ms: list[float]       # per frame: arrival (scheduled) -> result in host memory
+    latency_ms: list[float]       # per frame: arrival -> results in host memory
     server_latency_ms: list[float]  # per frame: submitted -> results in host memory (server clock)
     batch_frames: list[int]
     busy_retries: int
@@ -80,25 +80,31 @@ class TrafficReport:
 
 
 def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_of,
-                n_hyp: int, *, paced: bool = True, keep_results: bool = False):
+                n_hyp: int, *, paced: bool = True, keep_results: bool = False, submitters: int = 1):
     """Submit frames[a.radar] at each arrival's time (or as fast as the server
     takes them when paced is False) and collect every result.
 
-    seed_of(arrival) gives the frame's hypothesis seed.  Returns (report,
-    results) where results maps arrival index -> result dict when keep_results.
+    ``submitters`` threads share the radars (radar r goes to thread r mod
+    submitters), each submitting its radars' arrivals in time order, as one
+    feeder per group of sensors would.  A frame's latency is the time from its
+    arrival to the return of its submit (the copy into pinned memory, plus any
+    lateness of the submitting thread) plus the server's time from that copy to
+    results in host memory.  seed_of(arrival) gives the frame's hypothesis seed.
+    Returns (report, results) where results maps arrival index -> result dict
+    when keep_results.
     """
     evals_of = [int(n_hyp * np.diff(f.offsets.astype(np.int64))[np.diff(f.offsets) >= 2].sum())
                 for f in frames]
     tickets: list[tuple[int, Arrival, float]] = []
     cond = threading.Condition()
-    done_submitting = [False]
+    running = [submitters]
     results = {}
     lat, slat, bsz = [], [], []
     counters = {"busy": 0, "late": 0}
     errors = []
 
-    def submitter(t0):
-        for a in schedule:
+    def submitter(t0, mine):
+        for a in mine:
             if paced:
                 delay = t0 + a.t - time.perf_counter()
                 if delay > 0:
@@ -106,6 +112,7 @@ def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_
                 elif delay < -1e-3:
                     counters["late"] += 1
             f = frames[a.radar]
+            start = time.perf_counter()
             while True:
                 try:
                     tk = server.submit(f.theta, f.vd, f.offsets, seed_of(a))
@@ -113,40 +120,45 @@ def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_
                 except binding.RVError as e:
                     if e.code != binding.RV_ERR_BUSY:
                         errors.append(e)
-                        return
+                        break
                     counters["busy"] += 1
                     time.sleep(50e-6)
-            arrival = (t0 + a.t) if paced else time.perf_counter()
+            if errors:
+                break
+            arrival = (t0 + a.t) if paced else start
             with cond:
-                tickets.append((tk, a, arrival))
+                tickets.append((tk, a, time.perf_counter() - arrival))
                 cond.notify()
         with cond:
-            done_submitting[0] = True
+            running[0] -= 1
             cond.notify()
 
     t0 = time.perf_counter() + 0.01
-    th = threading.Thread(target=submitter, args=(t0,), daemon=True)
-    th.start()
+    parts = [[a for a in schedule if a.radar % submitters == i] for i in range(submitters)]
+    threads = [threading.Thread(target=submitter, args=(t0, part), daemon=True) for part in parts]
+    for th in threads:
+        th.start()
     got = 0
     t_last = t0
     while True:
         with cond:
-            while got >= len(tickets) and not done_submitting[0]:
+            while got >= len(tickets) and running[0] > 0:
                 cond.wait()
             if got >= len(tickets):
                 break
-            tk, a, arrival = tickets[got]
+            tk, a, pre = tickets[got]
         r = server.result(tk)
-        now = time.perf_counter()
-        t_last = now
-        lat.append((now - arrival) * 1e3)
+        t_last = time.perf_counter()
         tm = r["times"]
-        slat.append((tm["done_ns"] - tm["submitted_ns"]) * 1e-6)
+        server_ms = (tm["done_ns"] - tm["submitted_ns"]) * 1e-6
+        lat.append(pre * 1e3 + server_ms)
+        slat.append(server_ms)
         bsz.append(tm["batch_frames"])
         if keep_results:
             results[a.index] = r
         got += 1
-    th.join()
+    for th in threads:
+        th.join()
     if errors:
         raise errors[0]
     clusters = sum(frames[a.radar].n_clusters for a in schedule)
