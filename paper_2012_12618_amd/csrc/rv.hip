@@ -182,8 +182,9 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
     }
 }
 
-// Blocks [0, gridDim.x - 1) stage the points and clear the per-cluster best
-// keys; the last block plans the order (when `order` is non-null).
+// Block 0 plans the order (when `order` is non-null); it is dispatched first,
+// so the planning overlaps the staging.  Blocks [1, gridDim.x) stage the
+// points and clear the per-cluster best keys.
 __global__ __launch_bounds__(kPrepBlock) void prep_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
     float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
@@ -191,11 +192,11 @@ __global__ __launch_bounds__(kPrepBlock) void prep_kernel(
     int64_t n_words, const int32_t *__restrict__ off, int64_t n_clusters,
     int32_t *__restrict__ order, int64_t *__restrict__ n_big,
     unsigned long long *__restrict__ best_key) {
-    if (blockIdx.x == gridDim.x - 1) {
+    if (blockIdx.x == 0) {
         if (order != nullptr) plan_order(off, n_clusters, n_points, order, n_big);
         return;
     }
-    const int64_t p = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
+    const int64_t p = (int64_t)(blockIdx.x - 1) * kPrepBlock + threadIdx.x;
     if (p < n_clusters) best_key[p] = 0;
     if (p < n_points) {
         const float t = theta[p], v = vd[p];
