@@ -66,6 +66,31 @@ def profiled_traffic(workload: str, kernel: str = "score_kernel"):
     return rec["hbm_bytes_per_launch"]
 
 
+def profiled_valu_issue(workload: str):
+    """Vector-instruction issue of score_kernel from the committed SQ counters
+    (same kernel source only): instructions per SIMD per cycle at the clock the
+    chip held, against 0.25 for back-to-back full-rate wave64 FMAs."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", f"score_kernel_{workload}_counters.md")
+    src = os.path.join(ROOT, "paper_2012_12618_amd", "csrc", "rv.hip")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    sq = rec.get("sq")
+    if sq is None or rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    simds, xcds = 1024, 8
+    cycles = sq["GRBM_GUI_ACTIVE"] / xcds  # GRBM counts per XCD, summed over the 8
+    return {"valu_instructions_per_simd_cycle": sq["SQ_INSTS_VALU"] / (simds * cycles),
+            "salu_instructions_per_cu_cycle": sq["SQ_INSTS_SALU"] / (simds / 4 * cycles),
+            "clock_ghz": cycles / (rec["kernel_us"] * 1e3), "source": os.path.basename(path)}
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -472,10 +497,10 @@ def host_comparators(f, H):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="dense", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--latency-frames", type=int, default=200,
+    ap.add_argument("--latency-frames", type=int, default=1000,
                     help="frames timed from pinned host memory to results in host memory")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: min(16, cpus))")
@@ -505,6 +530,7 @@ def main() -> int:
         print("bench.py: run on a single rank", file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
 
     from paper_2012_12618_amd import binding, synth
@@ -545,20 +571,20 @@ def main() -> int:
     # own events around each kernel give per-kernel durations.
     binding.rv_stage_times()  # drop anything recorded before
     binding.rv_stage_timing(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    ev0.record(stream)
+    evs[0].record(stream)
     for i in range(args.steps):
         step(args.warmup + i)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     binding.rv_stage_timing(False)
     stage_ms, n_calls = binding.rv_stage_times()
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    ms_per_step = evs[0].elapsed_time(evs[-1]) / args.steps
+    step_times = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     sec = ms_per_step / 1e3
     evals_per_s = evals / sec
     clusters_per_s = K / sec
@@ -568,7 +594,9 @@ def main() -> int:
 
     # Frame latency: pinned host frame -> device -> estimate -> results in host memory.
     print(f"[bench] latency over {args.latency_frames} frames", file=sys.stderr, flush=True)
-    frames = [frame] + [synth.make_frame(synth.WORKLOADS[name][0], 1000 + f) for f in range(3)]
+    n_distinct = 8
+    frames = [frame] + [synth.make_frame(synth.WORKLOADS[name][0], 1000 + f)
+                        for f in range(n_distinct - 1)]
     slots = []
     for f in frames:
         h = tuple(torch.from_numpy(a).pin_memory() for a in (f.theta, f.vd, f.offsets))
@@ -625,6 +653,18 @@ def main() -> int:
                "sample": (f"{frames_done} whole {name} frame(s) ({K} clusters, {evals} evals each, "
                           f"fresh seeds), FP64, {dt:.2f} s wall on {threads} threads"),
                "clusters_per_s": frames_done * K / dt}
+        # One thread on every 8th cluster of the frame.
+        ids = np.arange(0, K, 8)
+        sizes = np.diff(frame.offsets.astype(np.int64))[ids]
+        ev1 = int(n_hyp * sizes[sizes >= 2].sum())
+        t0 = time.perf_counter()
+        oracle.estimate_velocity(frame.theta, frame.vd, frame.offsets, n_hyp, tau,
+                                 synth.ransac_seed(name, 30_000), cluster_ids=ids, want_mask=False,
+                                 n_threads=1)
+        dt1 = time.perf_counter() - t0
+        cpu["one_thread"] = {"value": ev1 / dt1, "unit": "hyp-point evals/s",
+                             "clusters_per_s": len(ids) / dt1,
+                             "sample": f"every 8th cluster ({len(ids)} clusters, {ev1} evals), {dt1:.2f} s"}
 
     line = {
         "metric": METRIC,
@@ -644,9 +684,10 @@ def main() -> int:
         "clusters_per_s": clusters_per_s,
         "frac_fp32_valu_peak": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
         "latency_ms": ({"p50": percentile(lat, 50), "p99": percentile(lat, 99), "frames": len(lat),
-                        "distinct_frames": 4,
+                        "distinct_frames": len(frames),
                         "scope": "pinned host frame -> H2D -> estimate -> D2H of per-cluster results"}
                        if lat else None),
+        "step_ms": {"median": percentile(step_times, 50), "p99": percentile(step_times, 99)},
         "stage_ms": dict(zip(binding.STAGE_NAMES, stage_avg)),
         "wall_ms_per_step": wall * 1e3 / args.steps,
         "roofline": {"bound": "alu", "kernel": "score_kernel", "achieved": achieved_tflops,
@@ -654,7 +695,8 @@ def main() -> int:
                      "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": profiled_traffic(name),
                      "algorithmic_flop_per_launch": FLOP_PER_EVAL * evals,
-                     "kernel_ms": score_ms},
+                     "kernel_ms": score_ms,
+                     "valu_issue": profiled_valu_issue(name)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
