@@ -309,7 +309,8 @@ typedef struct {
 int rv_server_stats(rv_server_t *server, rv_server_stats_t *stats);
 
 /* Finishes every submitted frame, stops the threads and frees everything;
-   results not taken are dropped. */
+   results not taken are dropped.  No other call on this server may be in
+   progress or start once destroy has begun. */
 void rv_server_destroy(rv_server_t *server);
 
 /* Message of the last failing call on this thread ("" if none). */
