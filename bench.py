@@ -39,6 +39,12 @@ WORKLOAD_TEXT = {
                "hypotheses, tau 0.15 m/s, FP32; frame server with a 16 GiB device budget, "
                "continuous batching over launch slots; frames from and results to host memory"),
 }
+WORKLOAD_TEXT["precision"] = (
+    "precision stress: 512 clusters of 65,536 points (theta U[-60,60] deg, (vx, vy) U[-30,30]^2 m/s, "
+    "noise sigma 0.05 m/s), 40% micro-Doppler band outliers +/-[0.5,2]|v|, 4096 hypotheses, "
+    "tau 0.15 m/s; FP16 residual form (half2 (cos, sin), v_dot2_f32_f16 onto a float32 offset "
+    "residual, widened threshold, exact float32 re-count of possible winners), FP64 refit; one "
+    "batched-form call per step")
 WORKLOAD_TEXT["paper-sweep"] = (
     "paper-literal variant (normalised line fit, MAD threshold, <= test, least-squares refit) "
     "on the shapes of the paper's Tables I and II: {8, 16, 32, 64} clusters x {100, 150} points, "
@@ -154,6 +160,9 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
         from paper_2012_12618_amd import tuner
 
         tuning = tuner.load(args.tuning, torch.cuda.get_device_name(dev), n_hyp)
+    if args.fp16_min_points > 0:
+        tuning = tuning or binding.rv_tuning_default()
+        tuning.fp16_min_points = args.fp16_min_points
     out = binding.allocate_batch_outputs(F, K, N, n_hyp, dev, want_near=True)
     stream = torch.cuda.current_stream(dev)
     graph = binding.rv_graph_capture_batch(theta, vd, offsets, fo, seeds, n_hyp, tau, out,
@@ -246,7 +255,7 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16" if tuning is not None and tuning.fp16_min_points > 0 else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[name], "frames": F, "clusters": K, "points": N,
                    "n_hyp": n_hyp, "tau": tau, "evals_per_step": evals,
@@ -289,13 +298,15 @@ def served_bench(args, torch, binding, synth, dev) -> int:
 
         tuning = tuner.load(args.tuning, torch.cuda.get_device_name(dev), n_hyp)
 
-    def make_server(max_batch, n_streams):
+    def make_server(max_batch, n_streams, fp16):
         cfg = binding.rv_server_config_default()
         cfg.n_hyp, cfg.tau = n_hyp, tau
         cfg.hbm_budget_bytes = 16 << 30
         cfg.max_batch_frames, cfg.n_streams = max_batch, n_streams
         if tuning is not None:
             cfg.tuning = tuning
+        if fp16 and args.fp16_min_points > 0:  # the served form only; the per-frame form stays FP32
+            cfg.tuning.fp16_min_points = args.fp16_min_points
         return binding.RVServer(cfg)
 
     def seed_of(a):
@@ -303,7 +314,7 @@ def served_bench(args, torch, binding, synth, dev) -> int:
 
     out = {}
     for form, (max_batch, n_streams) in (("served", (64, 2)), ("per_frame", (1, 1))):
-        server = make_server(max_batch, n_streams)
+        server = make_server(max_batch, n_streams, form == "served")
         try:
             print(f"[bench] {form}: warmup", file=sys.stderr, flush=True)
             serve.run_traffic(server, frames, warm, seed_of, n_hyp, paced=False,
@@ -360,9 +371,10 @@ def served_bench(args, torch, binding, synth, dev) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f16" if args.fp16_min_points > 0 else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[name], "radars": n_radars, "fps_per_radar": fps,
+                   "fp16_min_points": args.fp16_min_points,
                    "duration_s": args.duration, "frames": len(schedule), "n_hyp": n_hyp, "tau": tau,
                    "distinct_frame_contents": n_radars,
                    "value_scope": "frames submitted back to back from host memory, results back "
@@ -467,6 +479,135 @@ def paper_sweep_bench(args, torch, binding, synth, dev) -> int:
     return 0
 
 
+def precision_bench(args, torch, binding, synth, dev) -> int:
+    """Precision-stress shape: the FP16 residual form against the float32 form
+    on the same frame (both through the batched entry point, one frame), every
+    output compared bitwise, and the FP64 oracle on sampled clusters."""
+    import numpy as np
+
+    import oracle
+
+    print("[bench] generating precision workload", file=sys.stderr, flush=True)
+    frame, n_hyp, tau = synth.make_workload("precision")
+    K, N = frame.n_clusters, frame.n_points
+    evals = synth.evals_per_frame(frame.offsets, n_hyp)
+    theta = torch.from_numpy(frame.theta).to(dev)
+    vd = torch.from_numpy(frame.vd).to(dev)
+    offsets = torch.from_numpy(frame.offsets).to(dev)
+    fo = torch.tensor([0, K], dtype=torch.int32, device=dev)
+    seeds = torch.tensor([synth.ransac_seed("precision")], dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    fp16_min = args.fp16_min_points or 1024
+    forms = {}
+    for form, m in (("fp32", 0), ("fp16", fp16_min)):
+        tune = binding.rv_tuning_default()
+        tune.fp16_min_points = m
+        out = binding.allocate_batch_outputs(1, K, N, n_hyp, dev, want_near=True, want_bits=True,
+                                             debug=True)
+
+        def call(t=tune, o=out):
+            binding.rv_estimate_velocity_batch(theta, vd, offsets, fo, seeds, n_hyp, tau, tuning=t,
+                                               out=o, stream=stream)
+
+        print(f"[bench] {form} form: warmup {args.warmup}, {args.steps} steps", file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        binding.rv_stage_times()
+        binding.rv_stage_timing(True)
+        ev0.record(stream)
+        for _ in range(args.steps):
+            call()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        binding.rv_stage_timing(False)
+        stage_ms, n_calls = binding.rv_stage_times()
+        stage = dict(zip(binding.STAGE_NAMES, [x / max(n_calls, 1) for x in stage_ms]))
+        res = {k: v.cpu().numpy() for k, v in out.items() if k != "workspace"}
+        forms[form] = {"ms_per_step": ev0.elapsed_time(ev1) / args.steps, "stage_ms": stage, "res": res}
+    keys = ("vx", "vy", "heading", "n_inliers", "status", "n_near_tau", "inlier_bits")
+    identical = all(np.array_equal(forms["fp16"]["res"][k], forms["fp32"]["res"][k],
+                                   equal_nan=k in ("vx", "vy", "heading")) for k in keys)
+
+    # Error of the results against the FP64 oracle on sampled clusters; the
+    # same oracle run is the CPU baseline.
+    # Error of every result against the FP64 oracle, over clusters taken in
+    # rounds of `threads` spread across the frame until about 10 s of oracle
+    # wall time (or all of them); the same runs are the CPU baseline.
+    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    order = [k for r in range(max(1, K // threads)) for k in range(r, K, max(1, K // threads))]
+    ids, dt, rounds = [], 0.0, []
+    g = forms["fp16"]["res"]
+    o_parts = []
+    while len(ids) < K and (dt < 10.0 or not ids):
+        chunk = order[len(ids):len(ids) + threads]
+        print(f"[bench] oracle on clusters {chunk[0]}.. ({len(ids) + len(chunk)}/{K}), {threads} threads",
+              file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        o_parts.append(oracle.estimate_velocity(frame.theta, frame.vd, frame.offsets, n_hyp, tau,
+                                                synth.ransac_seed("precision"), cluster_ids=chunk,
+                                                want_mask=False, n_threads=threads))
+        dt += time.perf_counter() - t0
+        ids += chunk
+    o_vx = np.concatenate([p.vx for p in o_parts])
+    o_vy = np.concatenate([p.vy for p in o_parts])
+    o_hd = np.concatenate([p.heading for p in o_parts])
+    o_best = np.concatenate([p.best_hyp for p in o_parts])
+    idx = np.asarray(ids)
+    same = g["best_hyp"][idx] == o_best
+    dv = np.maximum(np.abs(g["vx"][idx].astype(np.float64) - o_vx), np.abs(g["vy"][idx].astype(np.float64) - o_vy))[same]
+    dh = np.abs(np.remainder(g["heading"][idx].astype(np.float64) - o_hd + np.pi, 2 * np.pi) - np.pi)[same]
+    ev_sample = int(sum((int(frame.offsets[k + 1]) - int(frame.offsets[k])) * n_hyp for k in ids))
+    cpu = None if args.no_cpu_baseline else {
+        "value": ev_sample / dt, "unit": "hyp-point evals/s", "cores": min(threads, len(ids)),
+        "kind": "oracle",
+        "sample": f"{len(ids)} clusters of 65,536 points x 4096 hypotheses, FP64, {dt:.2f} s wall"}
+
+    f16, f32 = forms["fp16"], forms["fp32"]
+    score16 = f16["stage_ms"]["score"]
+    achieved = FLOP_PER_EVAL * evals / (score16 / 1e3) / 1e12
+    sec = f16["ms_per_step"] / 1e3
+    line = {
+        "metric": METRIC,
+        "value": evals / sec,
+        "unit": "hyp-point evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f16["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["precision"], "clusters": K, "points": N, "n_hyp": n_hyp,
+                   "tau": tau, "evals_per_step": evals, "fp16_min_points": fp16_min},
+        "clusters_per_s": K / sec,
+        "fp32_form": {"ms_per_step": f32["ms_per_step"], "evals_per_s": evals / (f32["ms_per_step"] / 1e3),
+                      "stage_ms": f32["stage_ms"]},
+        "fp16_over_fp32_time": f16["ms_per_step"] / f32["ms_per_step"],
+        "outputs_bitwise_equal_to_fp32_form": identical,
+        "oracle_error": {"clusters": len(ids), "same_hypothesis": int(same.sum()),
+                         "abs_dv_mps": {"max": float(dv.max()) if dv.size else None,
+                                        "p50": float(np.median(dv)) if dv.size else None},
+                         "abs_dheading_rad": {"max": float(dh.max()) if dh.size else None,
+                                              "p50": float(np.median(dh)) if dh.size else None},
+                         "scope": "FP16-form results (bitwise the float32 form's) against the FP64 "
+                                  "oracle, per cluster; dv = max(|vx - vx_o|, |vy - vy_o|)"},
+        "stage_ms": f16["stage_ms"],
+        "roofline": {"bound": "alu", "kernel": "batch_score_kernel", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic_flop_per_launch": FLOP_PER_EVAL * evals, "kernel_ms": score16,
+                     "note": "the MI355X vector FP16 and FP32 peaks are the same 157.3 TFLOP/s"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if identical else 1
+
+
 def host_comparators(f, H):
     """The paper's host comparators on one frame: scikit-learn RANSACRegressor of
     v_d on theta per cluster (max_trials = H) and numpy.linalg.pinv per cluster."""
@@ -516,6 +657,10 @@ def main() -> int:
     ap.add_argument("--tuning", default="",
                     help="batched workload: JSON tuning table written by paper_2012_12618_amd.tuner "
                          "(default: the library's default setting)")
+    ap.add_argument("--fp16-min-points", type=int, default=0,
+                    help="batched and precision workloads: clusters of at least this many points "
+                         "take the FP16 residual form (precision default: 1024; batched default: "
+                         "none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (outside the timed "
                          "region), the reference kernel for scaling HBM byte counters")
@@ -545,6 +690,8 @@ def main() -> int:
         return served_bench(args, torch, binding, synth, dev)
     if name == "paper-sweep":
         return paper_sweep_bench(args, torch, binding, synth, dev)
+    if name == "precision":
+        return precision_bench(args, torch, binding, synth, dev)
     if name not in FRAME_WORKLOADS:
         return batch_bench(args, torch, binding, synth, dev)
     print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)

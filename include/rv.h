@@ -139,9 +139,19 @@ typedef struct {
     int32_t rows_max[RV_TUNE_BUCKETS];
     /* persistent scoring grid: workgroups per compute unit; 0 = as many as fit */
     int32_t blocks_per_cu;
+    /* clusters of at least this many points score their residuals in the FP16
+       form (0 = none, the default; >= 0).  The FP16 form: half2 (cos, sin) and
+       the float32 residual against a reference velocity, one v_dot2_f32_f16 per
+       point and hypothesis (FP32 accumulation), a threshold widened by a proven
+       bound on the FP16 error, then an exact float32 count of every hypothesis
+       that could still be the best.  It keeps the same hypothesis as the
+       float32 form, so every output is bitwise the same, except hyp_counts:
+       there it holds the FP16 counts, upper bounds of the float32 counts. */
+    int32_t fp16_min_points;
 } rv_tuning_t;
 
-/* Defaults: 16 rows in every bucket, as many workgroups per CU as fit. */
+/* Defaults: 16 rows in every bucket, as many workgroups per CU as fit, no
+   FP16 form. */
 void rv_tuning_default(rv_tuning_t *tuning);
 
 /* Device workspace bytes of rv_estimate_velocity_batch (0 for invalid sizes). */

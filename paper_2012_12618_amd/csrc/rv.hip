@@ -261,8 +261,9 @@ __device__ __forceinline__ uint32_t score_rows(const float2 *__restrict__ cs_chu
 }
 
 // Inlier counts of the wave's nh hypotheses (LDS at hp) over all points of the
-// cluster, rows_max (<= kRowsMax) register rows of points per pass; lane q
+// cluster, rows_max (<= kMaxRows) register rows of points per pass; lane q
 // returns the count of hypothesis q.
+template <int kMaxRows = kRowsMax>
 __device__ __forceinline__ uint32_t score_cluster(const Points &pts, Span sp, int lane,
                                                   const float4 *hp, int nh, float tau,
                                                   int rows_max) {
@@ -277,8 +278,11 @@ __device__ __forceinline__ uint32_t score_cluster(const Points &pts, Span sp, in
         const float2 *cs_chunk = pts.cs32 + base;
         const float *v_chunk = pts.v32 + base;
         switch (rows) {
-#define RV_ROWS(R) \
-    case R: total += score_rows<R>(cs_chunk, v_chunk, npts, lane, hp, ng, tau); break;
+#define RV_ROWS(R)                                                                   \
+    case R:                                                                          \
+        if constexpr (R <= kMaxRows)                                                 \
+            total += score_rows<R>(cs_chunk, v_chunk, npts, lane, hp, ng, tau);      \
+        break;
             RV_ROWS(1) RV_ROWS(2) RV_ROWS(3) RV_ROWS(4) RV_ROWS(5) RV_ROWS(6) RV_ROWS(7)
             RV_ROWS(8) RV_ROWS(9) RV_ROWS(10) RV_ROWS(11) RV_ROWS(12) RV_ROWS(13)
             RV_ROWS(14) RV_ROWS(15) RV_ROWS(16)
@@ -358,6 +362,280 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
     } else if (tid == 0) {
         for (int w = 1; w < kScoreBlock / kWave; ++w) key = s_key[w] > key ? s_key[w] : key;
         if (key != 0) atomicMax(&best_key[id.out], key);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP16 residual form of the scoring (batched form, clusters of at least
+// Tuning::fp16_min points).  It selects exactly the hypothesis the float32
+// form selects; only the work differs.
+//
+// Per workgroup (cluster, block of 256 hypotheses):
+//   1. reference velocity r = (rx, ry): the block's hypothesis with the most
+//      float32 inliers among the cluster's first kFp16Sample points;
+//   2. every point of a pass holds half2 (cos, sin) (rounded toward zero) and
+//      the float32 residual w = fma(-ry, sin, fma(-rx, cos, v_d)); hypothesis
+//      h = (hx, hy) arrives as half2 -(hx - rx, hy - ry), and one
+//      v_dot2_f32_f16 adds the two FP16 products to w in float32;
+//   3. the FP16 count hi_h uses the widened threshold tau + B_h, where B_h
+//      bounds |FP16 residual - float32 residual| at every point whose float32
+//      residual is below tau, so hi_h >= the float32 count n_h;
+//   4. the hypothesis with the largest (hi_h, lowest index) is counted exactly
+//      in float32 (T = its n_h); every other hypothesis with hi_h >= T is
+//      counted exactly too.  A hypothesis left out has n_h <= hi_h < T, so the
+//      block's best exact key, merged with the same 64-bit atomic maximum, is
+//      the float32 form's.
+//
+// Error bound (A = |hx - rx| + |hy - ry|, M = |hx| + |hy| + |rx| + |ry|, both
+// in float32; u = 2^-24): for a point with |float32 residual| < tau, the
+// terms are the rounding of w (about u (2|R| + 2A + M)), of -(h - r) to FP16
+// (2^-11 A) and of (cos, sin) toward zero (2^-10 A, plus 2^-24 A for FP16
+// subnormals), and the sums inside the dot product (at most 8u (2A + |R|));
+// together below 2^-9 A + 2^-20 (tau + M + 1).  B_h takes twice that,
+// 2^-8 A + 2^-18 (tau + M + 1), which also covers the float32 rounding of
+// tau + B_h.  A hypothesis with A >= 2^14 (or not finite) is not converted:
+// its FP16 row counts every finite point (threshold +inf), a valid upper bound.
+// ---------------------------------------------------------------------------
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+constexpr int kFp16Sample = 4 * kWave;  // points of the reference-velocity sample
+constexpr float kFp16MaxOffset = 16384.0f;
+
+// (bits of half2 -(h - r), widened threshold) of one hypothesis; an invalid
+// one (NaN) gets threshold 0, which no residual passes.
+__device__ __forceinline__ float2 fp16_hypothesis(float hx, float hy, float rx, float ry,
+                                                  float tau) {
+    if (__builtin_isnan(hx) || __builtin_isnan(hy)) return make_float2(0.0f, 0.0f);
+    const float dx = hx - rx, dy = hy - ry;
+    const float a = __builtin_fabsf(dx) + __builtin_fabsf(dy);
+    if (!(a < kFp16MaxOffset)) return make_float2(0.0f, __builtin_inff());
+    const float m = __builtin_fabsf(hx) + __builtin_fabsf(hy) + __builtin_fabsf(rx) +
+                    __builtin_fabsf(ry);
+    const float band = a * 0x1p-8f + (tau + m + 1.0f) * 0x1p-18f;
+    const half2_t nd = half2_t{(_Float16)(-dx), (_Float16)(-dy)};
+    return make_float2(__builtin_bit_cast(float, nd), tau + band);
+}
+
+// score_rows in the FP16 form: returns hi of hypothesis q of the wave in lane q.
+template <int R>
+__device__ __forceinline__ uint32_t score_rows_fp16(const float2 *__restrict__ cs_chunk,
+                                                    const float *__restrict__ v_chunk, int npts,
+                                                    int lane, const float4 *hp, int ng, float rx,
+                                                    float ry) {
+    half2_t cs[R];
+    float w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int len = npts - r * kWave;
+        cs[r] = half2_t{(_Float16)0.0f, (_Float16)0.0f};
+        w[r] = __builtin_inff();
+        if (lane < len) {
+            const float2 q = cs_chunk[r * kWave + lane];
+            const float v = v_chunk[r * kWave + lane];
+            cs[r] = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(q.x, q.y));
+            w[r] = __builtin_fmaf(-ry, q.y, __builtin_fmaf(-rx, q.x, v));
+        }
+    }
+    uint32_t counts = 0;
+    for (int g = 0; g < ng; ++g) {
+        const float4 h0 = hp[2 * g], h1 = hp[2 * g + 1];
+        const float hd[kHypGroup] = {h0.x, h0.z, h1.x, h1.z};
+        const float ht[kHypGroup] = {h0.y, h0.w, h1.y, h1.w};
+#pragma unroll
+        for (int u = 0; u < kHypGroup; ++u) {
+            const half2_t nd = __builtin_bit_cast(half2_t, hd[u]);
+            uint32_t n = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float e = __builtin_amdgcn_fdot2(cs[r], nd, w[r], false);
+                n += (uint32_t)__builtin_popcountll(
+                    __builtin_amdgcn_ballot_w64(__builtin_fabsf(e) < ht[u]));
+            }
+            counts = (uint32_t)amdgcn_writelane((int)n, g * kHypGroup + u, (int)counts);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    return counts;
+}
+
+// score_cluster in the FP16 form.
+__device__ __forceinline__ uint32_t score_cluster_fp16(const Points &pts, Span sp, int lane,
+                                                       const float4 *hp, int nh, int rows_max,
+                                                       float rx, float ry) {
+    const int ng = (nh + kHypGroup - 1) / kHypGroup;
+    const int64_t end = sp.lo + sp.n;
+    const int64_t pass = (int64_t)rows_max * kWave;
+    uint32_t total = 0;
+    for (int64_t base = sp.lo; base < end; base += pass) {
+        const int64_t left = end - base;
+        const int npts = (int)(left < pass ? left : pass);
+        const int rows = (npts + kWave - 1) / kWave;
+        const float2 *cs_chunk = pts.cs32 + base;
+        const float *v_chunk = pts.v32 + base;
+        switch (rows) {
+#define RV_ROWS16(R)                                                                       \
+    case R:                                                                                \
+        total += score_rows_fp16<R>(cs_chunk, v_chunk, npts, lane, hp, ng, rx, ry);        \
+        break;
+            RV_ROWS16(1) RV_ROWS16(2) RV_ROWS16(3) RV_ROWS16(4) RV_ROWS16(5) RV_ROWS16(6)
+            RV_ROWS16(7) RV_ROWS16(8) RV_ROWS16(9) RV_ROWS16(10) RV_ROWS16(11) RV_ROWS16(12)
+            RV_ROWS16(13) RV_ROWS16(14) RV_ROWS16(15) RV_ROWS16(16)
+#undef RV_ROWS16
+            default: break;
+        }
+    }
+    return total;
+}
+
+// Workgroup LDS of the FP16 form.
+struct Fp16Shared {
+    float4 h32[kScoreBlock / 2];               // float32 (vx, vy) of the block's hypotheses
+    float4 h16[kScoreBlock / 2];               // fp16_hypothesis() of each
+    float4 list[kWave / 2];                    // hypotheses counted exactly, float32
+    uint32_t part[kScoreBlock / kWave][kWave]; // per-wave partial exact counts
+    uint32_t idx[kScoreBlock];                 // candidates: positions in the block
+    unsigned long long key[kScoreBlock / kWave];
+    uint32_t n_cand[kScoreBlock / kWave];
+};
+
+constexpr int kExactRows = 8;  // register rows per pass of the exact counts
+
+__device__ __forceinline__ unsigned long long hyp_key(uint32_t count, int64_t h) {
+    return ((unsigned long long)count << 32) | (0xFFFFFFFFull - (uint32_t)h);
+}
+
+// Exact float32 counts of the nl (<= 64) hypotheses in sh.list over the whole
+// cluster; wave w scores rows [w rows/4, (w+1) rows/4) of the cluster.  Lane q
+// of every wave returns the count of list entry q.  Contains barriers.
+__device__ __forceinline__ uint32_t exact_counts(Span sp, const Points &pts, float tau, int nl,
+                                                 Fp16Shared &sh, int wave, int lane) {
+    const int64_t rows = (sp.n + kWave - 1) / kWave;
+    const int64_t r0 = rows * wave / (kScoreBlock / kWave);
+    const int64_t r1 = rows * (wave + 1) / (kScoreBlock / kWave);
+    const int64_t p1 = r1 * kWave < sp.n ? r1 * kWave : sp.n;
+    Span part;
+    part.lo = sp.lo + r0 * kWave;
+    part.n = p1 - r0 * kWave;
+    part.ok = true;
+    sh.part[wave][lane] = score_cluster<kExactRows>(pts, part, lane, sh.list, nl, tau, kExactRows);
+    __syncthreads();
+    uint32_t total = 0;
+#pragma unroll
+    for (int w = 0; w < kScoreBlock / kWave; ++w) total += sh.part[w][lane];
+    __syncthreads();
+    return total;
+}
+
+// One scoring block in the FP16 form (sp.ok and sp.n >= 2; called from the
+// persistent loop: every branch around a barrier is on a wave-uniform value).
+// hyp_counts, when requested, receives hi_h.
+__device__ __forceinline__ void score_block_fp16(Span sp, ClusterId id, int b, int32_t n_hyp,
+                                                 const Points &pts, float tau, int rows_max,
+                                                 Fp16Shared &sh,
+                                                 unsigned long long *__restrict__ best_key,
+                                                 int32_t *__restrict__ hyp_counts) {
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)b * kScoreBlock;
+    const int64_t h = base + tid;
+    float hx = __builtin_nanf(""), hy = __builtin_nanf("");
+    if (h < n_hyp) {
+        const Hypothesis hyp = make_hypothesis(pts, sp, (uint32_t)h, id.local, id.key0, id.key1);
+        hx = (float)hyp.vx;
+        hy = (float)hyp.vy;
+    }
+    float2 *h32 = reinterpret_cast<float2 *>(sh.h32);
+    h32[tid] = make_float2(hx, hy);
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = tid % kWave;
+    const int64_t w0 = base + wave * kWave;
+    const int nh = w0 < n_hyp ? ((int64_t)n_hyp - w0 < kWave ? (int)((int64_t)n_hyp - w0) : kWave)
+                              : 0;
+
+    // 1. Reference velocity from the sample.
+    Span sample = sp;
+    sample.n = sp.n < kFp16Sample ? sp.n : kFp16Sample;
+    unsigned long long key = 0;
+    if (nh > 0) {
+        const uint32_t cnt = score_cluster<kFp16Sample / kWave>(
+            pts, sample, lane, sh.h32 + wave * (kWave / 2), nh, tau, kFp16Sample / kWave);
+        if (lane < nh && !__builtin_isnan(h32[tid].x)) key = hyp_key(cnt, base + tid);
+    }
+    key = wave_max_u64(key);
+    if (lane == 0) sh.key[wave] = key;
+    __syncthreads();
+    unsigned long long ref = 0;
+#pragma unroll
+    for (int w = 0; w < kScoreBlock / kWave; ++w) ref = sh.key[w] > ref ? sh.key[w] : ref;
+    ref = uniform_u64(ref);
+    float rx = 0.0f, ry = 0.0f;
+    if (ref != 0) {
+        const float2 r = h32[(0xFFFFFFFFu - (uint32_t)ref) - (uint32_t)base];
+        if (__builtin_fabsf(r.x) + __builtin_fabsf(r.y) < kFp16MaxOffset) {
+            rx = r.x;
+            ry = r.y;
+        }
+    }
+    // The same value in every lane: kept in scalar registers.
+    rx = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, rx)));
+    ry = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, ry)));
+    reinterpret_cast<float2 *>(sh.h16)[tid] = fp16_hypothesis(hx, hy, rx, ry, tau);
+    __syncthreads();
+
+    // 2-3. FP16 upper-bound counts (the lane's own hypothesis is re-read from
+    // LDS afterwards rather than kept in registers through the loop).
+    uint32_t hi = 0;
+    if (nh > 0) hi = score_cluster_fp16(pts, sp, lane, sh.h16 + wave * (kWave / 2), nh, rows_max, rx, ry);
+    const bool valid = lane < nh && !__builtin_isnan(h32[tid].x);
+    if (hyp_counts != nullptr && lane < nh) hyp_counts[id.out * n_hyp + base + tid] = (int32_t)hi;
+    key = valid ? hyp_key(hi, base + tid) : 0ull;
+    key = wave_max_u64(key);
+    if (lane == 0) sh.key[wave] = key;
+    __syncthreads();
+    unsigned long long top = 0;
+#pragma unroll
+    for (int w = 0; w < kScoreBlock / kWave; ++w) top = sh.key[w] > top ? sh.key[w] : top;
+    top = uniform_u64(top);
+    if (top == 0) return;  // no valid hypothesis in this block
+
+    // 4. Exact count of the top hypothesis, then of every candidate.
+    const uint32_t h_top = 0xFFFFFFFFu - (uint32_t)top;
+    if (tid == 0) reinterpret_cast<float2 *>(sh.list)[0] = h32[h_top - (uint32_t)base];
+    __syncthreads();
+    const uint32_t t_exact = __builtin_amdgcn_readfirstlane(exact_counts(sp, pts, tau, 1, sh, wave, lane));
+    unsigned long long best = hyp_key(t_exact, h_top);
+    const bool cand = valid && (uint32_t)(base + tid) != h_top && hi >= t_exact;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(cand);
+    if (lane == 0) sh.n_cand[wave] = (uint32_t)__builtin_popcountll(m);
+    __syncthreads();
+    uint32_t before = 0, n_cand = 0;
+#pragma unroll
+    for (int w = 0; w < kScoreBlock / kWave; ++w) {
+        const uint32_t c = sh.n_cand[w];
+        before += w < wave ? c : 0u;
+        n_cand += c;
+    }
+    n_cand = __builtin_amdgcn_readfirstlane(n_cand);
+    if (cand) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        sh.idx[before + rank] = (uint32_t)tid;
+    }
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < n_cand; c0 += kWave) {
+        const int nl = n_cand - c0 < (uint32_t)kWave ? (int)(n_cand - c0) : kWave;
+        if (tid < nl) reinterpret_cast<float2 *>(sh.list)[tid] = h32[sh.idx[c0 + tid]];
+        __syncthreads();
+        const uint32_t cnt = exact_counts(sp, pts, tau, nl, sh, wave, lane);
+        unsigned long long k2 = 0;
+        if (lane < nl) k2 = hyp_key(cnt, base + sh.idx[c0 + lane]);
+        k2 = wave_max_u64(k2);
+        best = k2 > best ? k2 : best;
+    }
+    if (wave == 0) {
+        if (lane == 0) atomicMax(&best_key[id.out], best);
     }
 }
 
@@ -684,6 +962,7 @@ struct Batch {
 // bucket b holds n in [32 * 2^b, 64 * 2^b), the last bucket everything larger.
 struct Tuning {
     int32_t rows[RV_TUNE_BUCKETS];
+    int32_t fp16_min;  // clusters of at least this many points use the FP16 form; 0: none
 };
 
 // Everything the scoring and refit workgroups need about one cluster, at its
@@ -695,7 +974,8 @@ struct alignas(32) ItemDesc {
     uint32_t local;        // counter word 1: index within its frame
     uint32_t key0, key1;   // Philox key: its frame's seed
     int32_t ok;            // offsets valid
-    int32_t rows;          // register rows per pass for its size
+    int16_t rows;          // register rows per pass for its size
+    int16_t fp16;          // scored in the FP16 residual form
 };
 
 constexpr int kQueueStride = 32;  // 64-bit counters: 256 bytes between queues
@@ -823,7 +1103,8 @@ __global__ __launch_bounds__(kPrepBlock) void batch_scatter_kernel(
     d.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
     d.key1 = (uint32_t)(seed >> 32);
     d.ok = sp.ok ? 1 : 0;
-    d.rows = tune.rows[size_bucket(sp.n)];
+    d.rows = (int16_t)tune.rows[size_bucket(sp.n)];
+    d.fp16 = (int16_t)(tune.fp16_min > 0 && sp.ok && sp.n >= 2 && sp.n >= tune.fp16_min ? 1 : 0);
     desc[base[cls] + rank] = d;
 }
 
@@ -833,7 +1114,11 @@ __global__ __launch_bounds__(kPrepBlock) void batch_scatter_kernel(
 // such as threadIdx.x == 0 the compiler may thread that guard across the
 // loop's back edge into a lane-masked inner loop that lane 0 leaves to fetch
 // the next item while lanes 1..63 wait on the old one.  Seven waves per SIMD
-// keep the loop state out of spill code in the scoring passes.
+// keep the loop state out of spill code in the scoring passes.  kFp16: the
+// instantiation that also runs FP16-form items (launched only when the tuning
+// enables that form, so that the float32-only kernel keeps its own register
+// allocation).
+template <bool kFp16>
 __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))) void batch_score_kernel(
     const ItemDesc *__restrict__ desc, int64_t n_clusters, int32_t n_hyp,
     int32_t blocks_per_cluster, Points pts, float tau, unsigned long long *__restrict__ queues,
@@ -841,6 +1126,7 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))
     __shared__ float4 s_hyp[kScoreBlock / 2];
     __shared__ unsigned long long s_key[kScoreBlock / kWave];
     __shared__ unsigned long long s_item;
+    __shared__ Fp16Shared s_fp16;  // unreferenced, so not allocated, when !kFp16
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const uint32_t home = blockIdx.x % kXcds;
@@ -862,6 +1148,13 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(7))
             const int64_t j = (int64_t)q + (int64_t)kXcds * (int64_t)(item / bpc);
             const int b = (int)(item % bpc);
             const ItemDesc d = desc[j];
+            if constexpr (kFp16) {
+                if (d.fp16 != 0) {
+                    score_block_fp16(desc_span(d), desc_id(d), b, n_hyp, pts, tau, d.rows, s_fp16,
+                                     best_key, hyp_counts);
+                    continue;
+                }
+            }
             score_block<true>(desc_span(d), desc_id(d), b, n_hyp, pts, tau, d.rows, s_hyp, s_key,
                               best_key, hyp_counts);
         }
@@ -997,6 +1290,8 @@ int check_batch(const BatchArgs &a) {
             return fail(RV_ERR_INVALID_ARG, "tuning.rows_max must be in [1, %d]", kRowsMax);
     if (a.tuning.blocks_per_cu < 0 || a.tuning.blocks_per_cu > 64)
         return fail(RV_ERR_INVALID_ARG, "tuning.blocks_per_cu must be in [0, 64]");
+    if (a.tuning.fp16_min_points < 0)
+        return fail(RV_ERR_INVALID_ARG, "tuning.fp16_min_points must be >= 0");
     const BatchLayout L = make_batch_layout(a.n_clusters, a.n_points);
     if (a.workspace == nullptr || a.workspace_bytes < L.total)
         return fail(RV_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
@@ -1039,12 +1334,13 @@ void launch_refit(bool batch, const int32_t *off, const int32_t *order, const It
 }
 
 // Persistent grid of the batched scoring kernel on the current device.
-int persistent_blocks(int blocks_per_cu, int64_t items, unsigned *grid) {
+int persistent_blocks(int blocks_per_cu, bool fp16, int64_t items, unsigned *grid) {
     int fit = 0;
     const int cus = device_cus();
-    if (cus <= 0 ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_score_kernel, kScoreBlock, 0) !=
-            hipSuccess)
+    const hipError_t e =
+        fp16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_score_kernel<true>, kScoreBlock, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, batch_score_kernel<false>, kScoreBlock, 0);
+    if (cus <= 0 || e != hipSuccess)
         return fail(RV_ERR_HIP, "device query failed");
     int per_cu = blocks_per_cu > 0 && blocks_per_cu < fit ? blocks_per_cu : fit;
     if (per_cu < 1) per_cu = 1;
@@ -1079,6 +1375,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     bt.n_frames = a.n_frames;
     Tuning tune;
     for (int b = 0; b < RV_TUNE_BUCKETS; ++b) tune.rows[b] = a.tuning.rows_max[b];
+    tune.fp16_min = a.tuning.fp16_min_points;
     const int64_t bpc = batch_blocks_per_cluster(a);
     const int64_t n_words = a.o.bits != nullptr ? (a.n_points + 31) / 32 : 0;
     int64_t prep_items = a.n_points > n_words ? a.n_points : n_words;
@@ -1096,9 +1393,14 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
                        dim3((unsigned)((a.n_clusters + kPrepBlock - 1) / kPrepBlock)),
                        dim3(kPrepBlock), 0, st, a.off, a.n_clusters, a.n_points, bt, tune, hist, desc);
     if (timed) (void)hipEventRecord(tc.ev[1], st);
-    hipLaunchKernelGGL(batch_score_kernel, dim3(grid), dim3(kScoreBlock), 0, st,
-                       (const ItemDesc *)desc, a.n_clusters, a.n_hyp, (int32_t)bpc, pts, a.tau,
-                       queues, best_key, a.o.hyp_counts);
+    if (a.tuning.fp16_min_points > 0)
+        hipLaunchKernelGGL(batch_score_kernel<true>, dim3(grid), dim3(kScoreBlock), 0, st,
+                           (const ItemDesc *)desc, a.n_clusters, a.n_hyp, (int32_t)bpc, pts, a.tau,
+                           queues, best_key, a.o.hyp_counts);
+    else
+        hipLaunchKernelGGL(batch_score_kernel<false>, dim3(grid), dim3(kScoreBlock), 0, st,
+                           (const ItemDesc *)desc, a.n_clusters, a.n_hyp, (int32_t)bpc, pts, a.tau,
+                           queues, best_key, a.o.hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
     launch_refit(true, nullptr, nullptr, (const ItemDesc *)desc, a.n_clusters, n_big, a.n_points,
                  0, 0, pts, best_key, a.tau, a.o, st);
@@ -1303,6 +1605,7 @@ void rv_tuning_default(rv_tuning_t *t) {
     if (t == nullptr) return;
     for (int b = 0; b < RV_TUNE_BUCKETS; ++b) t->rows_max[b] = kRowsMax;
     t->blocks_per_cu = 0;
+    t->fp16_min_points = 0;
 }
 
 size_t rv_batch_workspace_bytes(int64_t n_frames, int64_t n_clusters, int64_t n_points,
@@ -1327,7 +1630,8 @@ int rv_estimate_velocity_batch(const float *theta, const float *vd, const int32_
     if (int rc = check_batch(a)) return rc;
     unsigned grid = 1;
     if (a.n_clusters > 0)
-        if (int rc = persistent_blocks(a.tuning.blocks_per_cu, a.n_clusters * batch_blocks_per_cluster(a), &grid))
+        if (int rc = persistent_blocks(a.tuning.blocks_per_cu, a.tuning.fp16_min_points > 0,
+                                     a.n_clusters * batch_blocks_per_cluster(a), &grid))
             return rc;
     return launch_batch(a, grid, (hipStream_t)stream, true);
 }
@@ -1354,7 +1658,8 @@ int rv_graph_capture_batch(const float *theta, const float *vd, const int32_t *c
     if (int rc = check_batch(a)) return rc;
     unsigned grid = 1;
     if (a.n_clusters > 0)
-        if (int rc = persistent_blocks(a.tuning.blocks_per_cu, a.n_clusters * batch_blocks_per_cluster(a), &grid))
+        if (int rc = persistent_blocks(a.tuning.blocks_per_cu, a.tuning.fp16_min_points > 0,
+                                     a.n_clusters * batch_blocks_per_cluster(a), &grid))
             return rc;
     hipStream_t cap = nullptr;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)

@@ -425,6 +425,8 @@ int check_config(const rv_server_config_t *c) {
             return fail(RV_ERR_INVALID_ARG, "tuning.rows_max must be in [1, 16]");
     if (c->tuning.blocks_per_cu < 0 || c->tuning.blocks_per_cu > 64)
         return fail(RV_ERR_INVALID_ARG, "tuning.blocks_per_cu must be in [0, 64]");
+    if (c->tuning.fp16_min_points < 0)
+        return fail(RV_ERR_INVALID_ARG, "tuning.fp16_min_points must be >= 0");
     return RV_OK;
 }
 

@@ -80,13 +80,16 @@ class Frame:
 # "small": 64 clusters of U{20..200} points, 20 % uniform outliers, 256 hypotheses.
 # "dense": 4096 clusters, log-uniform sizes in [8, 4096], 30 % outliers split evenly
 #          between uniform and micro-Doppler band outliers, 1024 hypotheses.
+# "precision": 512 clusters of 65,536 points, 40 % micro-Doppler band outliers,
+#          4096 hypotheses (the precision-stress shape of the FP16 residual form).
 WORKLOADS = {
     "small": (FrameSpec(64, "uniform", 20, 200, p_uniform=0.20), 256, 0.15),
     "dense": (FrameSpec(4096, "loguniform", 8, 4096, p_uniform=0.15, p_band=0.15), 1024, 0.15),
+    "precision": (FrameSpec(512, "fixed", 65536, 65536, p_uniform=0.0, p_band=0.40), 4096, 0.15),
 }
 # Data seed of each workload and the per-frame hypothesis seed convention:
 # hypothesis seed = (workload number << 32) | frame index.
-WORKLOAD_NUMBER = {"small": 1, "dense": 2, "batched": 3, "served": 4, "paper": 5}
+WORKLOAD_NUMBER = {"small": 1, "dense": 2, "batched": 3, "served": 4, "paper": 5, "precision": 6}
 
 
 @dataclasses.dataclass(frozen=True)

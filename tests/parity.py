@@ -54,16 +54,30 @@ def run_gpu(theta, vd, offsets, n_hyp, tau, seed, *, debug=True, bits=True, devi
     return out
 
 
-def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True) -> dict:
-    """Apply the protocol to GPU outputs ``g`` and oracle result ``o`` (debug run)."""
+def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True,
+          cluster_ids=None) -> dict:
+    """Apply the protocol to GPU outputs ``g`` and oracle result ``o`` (debug run).
+
+    With ``cluster_ids``, ``o`` holds only those clusters (oracle run with the
+    same list) while ``g`` holds the whole frame; only the listed clusters are
+    checked."""
     import oracle
 
     offsets = np.asarray(offsets, dtype=np.int64)
-    K = len(offsets) - 1
+    K_all = len(offsets) - 1
+    ids = np.arange(K_all) if cluster_ids is None else np.asarray(cluster_ids, dtype=np.int64)
+    K = len(ids)
     stats = {"clusters": K, "ambiguous_selection": 0, "mask_diff_points": 0, "max_dv": 0.0,
              "max_dheading": 0.0, "hyp_checked": 0}
+    if cluster_ids is not None:
+        g = dict(g)
+        for key in ("vx", "vy", "heading", "n_inliers", "status", "n_near_tau", "best_hyp"):
+            if key in g:
+                g[key] = g[key][ids]
+        if "hyp_counts" in g:
+            g["hyp_counts"] = g["hyp_counts"].reshape(K_all, n_hyp)[ids]
     assert np.array_equal(g["status"], o.status), (
-        f"status differs at clusters {np.flatnonzero(g['status'] != o.status)[:10]}")
+        f"status differs at clusters {ids[np.flatnonzero(g['status'] != o.status)][:10]}")
     if K == 0:
         return stats
 
@@ -82,26 +96,27 @@ def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True) -
         stats["hyp_checked"] = int(valid.sum())
 
     gmask = g.get("mask")
-    for k in range(K):
-        st = int(o.status[k])
+    for i in range(K):
+        k = int(ids[i])
+        st = int(o.status[i])
         if st in (oracle.CLUSTER_TOO_FEW_POINTS, oracle.CLUSTER_BAD_OFFSETS,
                   oracle.CLUSTER_ALL_DEGENERATE):
-            assert g["n_inliers"][k] == 0
-            assert math.isnan(g["vx"][k]) and math.isnan(g["vy"][k]) and math.isnan(g["heading"][k])
-            assert g["best_hyp"][k] == -1
+            assert g["n_inliers"][i] == 0
+            assert math.isnan(g["vx"][i]) and math.isnan(g["vy"][i]) and math.isnan(g["heading"][i])
+            assert g["best_hyp"][i] == -1
             continue
         lo, hi = int(offsets[k]), int(offsets[k + 1])
-        hg, ho = int(g["best_hyp"][k]), int(o.best_hyp[k])
+        hg, ho = int(g["best_hyp"][i]), int(o.best_hyp[i])
         if hg == ho:
-            ref_vx, ref_vy, ref_hd = o.vx[k], o.vy[k], o.heading[k]
-            ref_n, ref_near = int(o.n_inliers[k]), int(o.n_near_tau[k])
+            ref_vx, ref_vy, ref_hd = o.vx[i], o.vy[i], o.heading[i]
+            ref_n, ref_near = int(o.n_inliers[i]), int(o.n_near_tau[i])
             ref_mask = o.inlier_mask[lo:hi].astype(bool) if o.inlier_mask is not None else None
             ref_nearmask = None
             ref_status = st
         else:
             assert check_hyp, f"cluster {k}: gpu kept h={hg}, oracle h={ho}"
-            valid = o.hyp_valid[k].astype(bool)
-            clo, chi = o.hyp_count_lo[k], o.hyp_count_hi[k]
+            valid = o.hyp_valid[i].astype(bool)
+            clo, chi = o.hyp_count_lo[i], o.hyp_count_hi[i]
             m_lo = clo[valid].max()
             cand = valid & (chi >= m_lo)
             assert (clo[cand] != chi[cand]).any(), (
@@ -113,7 +128,7 @@ def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True) -
             ref_vx, ref_vy, ref_hd = f.vx, f.vy, f.heading
             ref_n, ref_near = f.n_inliers, f.n_near_tau
             ref_mask, ref_nearmask, ref_status = f.mask.astype(bool), f.near_mask.astype(bool), f.status
-        assert int(g["status"][k]) == ref_status
+        assert int(g["status"][i]) == ref_status
         masks_equal = True
         if gmask is not None and ref_mask is not None:
             diff = np.flatnonzero(gmask[lo:hi] != ref_mask)
@@ -126,18 +141,18 @@ def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True) -
                 stats["mask_diff_points"] += int(diff.size)
                 masks_equal = False
         if masks_equal:
-            assert int(g["n_inliers"][k]) == ref_n, f"cluster {k}: n_inliers {g['n_inliers'][k]} vs {ref_n}"
+            assert int(g["n_inliers"][i]) == ref_n, f"cluster {k}: n_inliers {g['n_inliers'][i]} vs {ref_n}"
             if "n_near_tau" in g:
-                assert int(g["n_near_tau"][k]) == ref_near
+                assert int(g["n_near_tau"][i]) == ref_near
         if ref_status != oracle.CLUSTER_OK:
             continue
         if masks_equal:
-            dv = max(abs(float(g["vx"][k]) - ref_vx), abs(float(g["vy"][k]) - ref_vy))
+            dv = max(abs(float(g["vx"][i]) - ref_vx), abs(float(g["vy"][i]) - ref_vy))
             stats["max_dv"] = max(stats["max_dv"], dv)
             assert dv <= V_TOL, f"cluster {k}: |dv| = {dv}"
             speed = math.hypot(ref_vx, ref_vy)
             if speed >= 0.01:
-                dh = abs(math.remainder(float(g["heading"][k]) - ref_hd, 2 * math.pi))
+                dh = abs(math.remainder(float(g["heading"][i]) - ref_hd, 2 * math.pi))
                 stats["max_dheading"] = max(stats["max_dheading"], dh)
                 assert dh <= 2e-4 / speed + 1e-6, f"cluster {k}: heading off by {dh}"
     return stats
