@@ -527,6 +527,7 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
         stage = dict(zip(binding.STAGE_NAMES, [x / max(n_calls, 1) for x in stage_ms]))
         res = {k: v.cpu().numpy() for k, v in out.items() if k != "workspace"}
         forms[form] = {"ms_per_step": ev0.elapsed_time(ev1) / args.steps, "stage_ms": stage, "res": res}
+    calibration_copy(torch, dev, args.copy_calibration_mb)
     keys = ("vx", "vy", "heading", "n_inliers", "status", "n_near_tau", "inlier_bits")
     identical = all(np.array_equal(forms["fp16"]["res"][k], forms["fp32"]["res"][k],
                                    equal_nan=k in ("vx", "vy", "heading")) for k in keys)
@@ -599,7 +600,8 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
         "stage_ms": f16["stage_ms"],
         "roofline": {"bound": "alu", "kernel": "batch_score_kernel", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": profiled_traffic("precision", "batch_score_kernel"),
                      "algorithmic_flop_per_launch": FLOP_PER_EVAL * evals, "kernel_ms": score16,
                      "note": "the MI355X vector FP16 and FP32 peaks are the same 157.3 TFLOP/s"},
         "cpu_baseline": cpu,
