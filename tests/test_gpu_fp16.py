@@ -13,7 +13,9 @@
 * the precision-stress shape at full size (512 clusters of 65,536 points, 40 %
   micro-Doppler band outliers, 4096 hypotheses): FP16 form bitwise the float32
   form, and the parity protocol against the FP64 oracle on sampled clusters,
-  with the error of each sampled result printed.
+  with the error of each sampled result printed;
+* the FP16 form captured in a HIP graph (replays with eager work and new
+  contents in between) and inside the frame server.
 """
 import numpy as np
 import pytest
@@ -179,3 +181,62 @@ def test_fp16_precision_stress_full_size(rv, oracle_mod):
               f"err {abs(g16['vy'][k] - o.vy[i]):.2e}), heading err "
               f"{abs(np.remainder(g16['heading'][k] - o.heading[i] + np.pi, 2 * np.pi) - np.pi):.2e}, "
               f"inliers {g16['n_inliers'][k]} (oracle {o.n_inliers[i]})", flush=True)
+
+
+def test_fp16_form_in_a_captured_graph(rv):
+    """Graph replays of the FP16 form, with eager work and new contents between
+    replays, equal the eager float32 form bitwise (every output but hyp_counts)."""
+    batch, H, tau = synth.make_batch_workload("served", n_frames=3)
+    f = batch.frame
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    t, v, o = dev(f.theta), dev(f.vd), dev(f.offsets)
+    fo, sd = dev(batch.frame_offsets), dev(batch.seeds.view(np.int64))
+    K, N, F = f.n_clusters, f.n_points, batch.n_frames
+    t16 = rv.rv_tuning_default()
+    t16.fp16_min_points = 64
+    eager = rv.allocate_batch_outputs(F, K, N, H, "cuda:0", want_bits=True, debug=True)
+    replay = rv.allocate_batch_outputs(F, K, N, H, "cuda:0", want_bits=True, debug=True)
+    print(f"[gpu] rv_graph_capture_batch fp16_min=64 F={F} K={K} N={N} H={H}", flush=True)
+    graph = rv.rv_graph_capture_batch(t, v, o, fo, sd, H, tau, replay, tuning=t16)
+    try:
+        for rep in range(3):
+            if rep == 1:
+                v.neg_()
+            if rep == 2:
+                sd.add_(11)
+            rv.rv_estimate_velocity_batch(t, v, o, fo, sd, H, tau, out=eager)  # float32 form
+            _ = torch.ones(1000, device="cuda").sum().item()
+            torch.cuda.synchronize()
+            print(f"[gpu] fp16 graph replay {rep}", flush=True)
+            graph.launch()
+            torch.cuda.synchronize()
+            for k in KEYS:
+                a, b = eager[k].cpu().numpy(), replay[k].cpu().numpy()
+                assert np.array_equal(a, b, equal_nan=k in ("vx", "vy", "heading")), (rep, k)
+            assert np.all(replay["hyp_counts"].cpu().numpy() >= eager["hyp_counts"].cpu().numpy())
+    finally:
+        graph.destroy()
+
+
+def test_server_with_fp16_form_matches_single_frames(rv):
+    """A frame server whose tuning enables the FP16 form answers every frame
+    with the float32 single-frame results."""
+    batch, H, tau = synth.make_batch_workload("served", n_frames=4)
+    frames = [batch.frame_slice(f) for f in range(batch.n_frames)]
+    cfg = rv.rv_server_config_default()
+    cfg.n_hyp, cfg.tau = H, tau
+    cfg.max_batch_frames, cfg.n_streams = 2, 2
+    cfg.tuning.fp16_min_points = 128
+    print(f"[gpu] server fp16_min=128 frames={len(frames)}", flush=True)
+    server = rv.RVServer(cfg)
+    try:
+        seeds = [synth.frame_seed("served", 900 + i) for i in range(len(frames))]
+        tickets = [server.submit(f.theta, f.vd, f.offsets, s) for f, s in zip(frames, seeds)]
+        got = [server.result(tk) for tk in tickets]
+    finally:
+        server.destroy()
+    for f, s, g in zip(frames, seeds, got):
+        alone = parity.run_gpu(f.theta, f.vd, f.offsets, H, tau, s, debug=False, bits=False,
+                               label="fp16-server-alone")
+        for k in ("vx", "vy", "heading", "n_inliers", "status", "n_near_tau"):
+            assert np.array_equal(g[k], alone[k], equal_nan=k in ("vx", "vy", "heading")), k
