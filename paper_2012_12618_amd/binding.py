@@ -211,6 +211,15 @@ def allocate_outputs(n_clusters: int, n_points: int, n_hyp: int, device, *,
     return out
 
 
+def _used_on(stream, tensors) -> None:
+    """Tell torch's caching allocator that ``stream`` uses these tensors, so that
+    their memory is not handed out again (for instance after the workspace is
+    dropped on return) before the work enqueued on ``stream`` has finished."""
+    for t in tensors:
+        if isinstance(t, torch.Tensor) and t.is_cuda:
+            t.record_stream(stream)
+
+
 def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
                          n_hyp: int, tau: float, seed: int, *, want_near: bool = True,
                          want_bits: bool = False, debug: bool = False, out: dict | None = None,
@@ -240,6 +249,7 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
         off = offsets.cpu()
         if off[0] != 0 or off[-1] != n_points or bool((off[1:] < off[:-1]).any()):
             raise ValueError("offsets must start at 0, be non-decreasing and end at n_points")
+    owned = out is None
     if out is None:
         out = allocate_outputs(n_clusters, n_points, n_hyp, device, want_near=want_near,
                                want_bits=want_bits, debug=debug)
@@ -263,6 +273,8 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
         ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream),
     )
     _check(code)
+    if owned:
+        _used_on(stream, out.values())
     return {k: v for k, v in out.items() if k != "workspace"}
 
 
@@ -371,6 +383,7 @@ def rv_estimate_velocity_batch(theta, vd, offsets, frame_offsets, seeds, n_hyp: 
     n_points = int(theta.numel())
     n_clusters = int(offsets.numel()) - 1
     n_frames = int(frame_offsets.numel()) - 1
+    owned = out is None
     if out is None:
         out = allocate_batch_outputs(n_frames, n_clusters, n_points, n_hyp, theta.device,
                                      want_near=want_near, want_bits=want_bits, debug=debug)
@@ -378,6 +391,8 @@ def rv_estimate_velocity_batch(theta, vd, offsets, frame_offsets, seeds, n_hyp: 
     if stream is None:
         stream = torch.cuda.current_stream(theta.device)
     _check(lib.rv_estimate_velocity_batch(*args, ctypes.c_void_p(stream.cuda_stream)))
+    if owned:
+        _used_on(stream, out.values())
     return {k: v for k, v in out.items() if k != "workspace"}
 
 
@@ -462,7 +477,7 @@ def rv_estimate_velocity_paper(theta: torch.Tensor, vd: torch.Tensor, offsets: t
         _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
         _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
         ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream)))
-    out["_workspace"] = ws  # keep alive until the stream has used it
+    _used_on(stream, list(out.values()) + [ws])
     return out
 
 
