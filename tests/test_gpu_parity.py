@@ -231,3 +231,27 @@ def test_parity_precision_stress_shape(rv, oracle_mod):
     spec = synth.FrameSpec(8, "fixed", 65536, 65536, p_uniform=0.0, p_band=0.4)
     frame = synth.make_frame(spec, seed=505)
     _parity(oracle_mod, "stress-65536x4096", frame.theta, frame.vd, frame.offsets, 4096, 0.15, 505)
+
+
+def test_side_stream_call_keeps_its_workspace(rv):
+    """A call on a non-current stream with binding-allocated buffers: the
+    workspace dropped on return must not be handed to the current stream's
+    next allocation while the side stream still uses it."""
+    frame, H, tau = synth.make_workload("small")
+    seed = synth.ransac_seed("small")
+    t = torch.from_numpy(frame.theta).cuda()
+    v = torch.from_numpy(frame.vd).cuda()
+    o = torch.from_numpy(frame.offsets).cuda()
+    ref = rv.rv_estimate_velocity(t, v, o, H, tau, seed)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    print("[gpu] rv_estimate_velocity on a side stream", flush=True)
+    for rep in range(3):
+        got = rv.rv_estimate_velocity(t, v, o, H, tau, seed, stream=side)
+        junk = torch.full((1 << 22,), float("nan"), device="cuda")  # current stream
+        junk.add_(1.0)
+        side.synchronize()
+        torch.cuda.synchronize()
+        for k in ("vx", "vy", "heading", "n_inliers", "status"):
+            assert torch.equal(torch.nan_to_num(got[k].float(), 7.0), torch.nan_to_num(ref[k].float(), 7.0)), (rep, k)
