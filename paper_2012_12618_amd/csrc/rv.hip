@@ -182,6 +182,23 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
     }
 }
 
+// Stages point p: FP64 sincos of its azimuth, float32 (cos, sin) and v_d for
+// scoring, FP64 (cos, sin) for the solves and the refit.  A non-finite point
+// is staged as (0, 0, +inf): its float32 residual is inf or NaN, never below
+// tau, and +inf marks it for the solves and the refit.
+__device__ __forceinline__ void stage_point(const float *__restrict__ theta,
+                                            const float *__restrict__ vd, int64_t p,
+                                            float2 *__restrict__ cs32, float *__restrict__ v32,
+                                            double2 *__restrict__ cs64) {
+    const float t = theta[p], v = vd[p];
+    double s, c;
+    sincos((double)t, &s, &c);
+    const bool ok = isfinite(t) && isfinite(v);
+    cs32[p] = make_float2(ok ? (float)c : 0.0f, ok ? (float)s : 0.0f);
+    v32[p] = ok ? v : __builtin_inff();
+    cs64[p] = make_double2(c, s);
+}
+
 // Block 0 plans the order (when `order` is non-null); it is dispatched first,
 // so the planning overlaps the staging.  Blocks [1, gridDim.x) stage the
 // points and clear the per-cluster best keys.
@@ -198,18 +215,7 @@ __global__ __launch_bounds__(kPrepBlock) void prep_kernel(
     }
     const int64_t p = (int64_t)(blockIdx.x - 1) * kPrepBlock + threadIdx.x;
     if (p < n_clusters) best_key[p] = 0;
-    if (p < n_points) {
-        const float t = theta[p], v = vd[p];
-        double s, c;
-        sincos((double)t, &s, &c);
-        const bool ok = isfinite(t) && isfinite(v);
-        // A non-finite point is staged as (0, 0, +inf): its float32 residual is
-        // inf or NaN, never below tau, and +inf marks it for the solves and the
-        // refit.
-        cs32[p] = make_float2(ok ? (float)c : 0.0f, ok ? (float)s : 0.0f);
-        v32[p] = ok ? v : __builtin_inff();
-        cs64[p] = make_double2(c, s);
-    }
+    if (p < n_points) stage_point(theta, vd, p, cs32, v32, cs64);
     if (bits != nullptr && p < n_words) bits[p] = 0u;
 }
 
@@ -952,6 +958,42 @@ __global__ __launch_bounds__(kRefitBlock) void refit_kernel(
 // and no counter is hammered by the whole chip; a workgroup whose queue is
 // empty takes items from the others.
 
+// Small frames (see use_small_frame_path): one workgroup per cluster stages the
+// cluster's own points, scores its hypotheses (at most 256: one block), keeps
+// the best and refits, in a single launch.  The arithmetic is the three-kernel
+// path's, so every output is bitwise the same; these frames are bound by
+// launch latency, and one launch replaces three.  A workgroup reads back only
+// points it staged itself, after a workgroup barrier (its waves share the
+// compute unit's L1, which its own stores keep current).
+__global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))) void small_frame_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd, const int32_t *__restrict__ off,
+    int64_t n_points, int32_t n_hyp, uint32_t key0, uint32_t key1, Points pts, float tau,
+    float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
+    unsigned long long *__restrict__ best_key, Outputs o) {
+    __shared__ float4 s_hyp[kScoreBlock / 2];
+    __shared__ unsigned long long s_key[kScoreBlock / kWave];
+    __shared__ double s_sum[kRefitBlock / kWave][5];
+    __shared__ int s_cnt[kRefitBlock / kWave][2];
+    const int64_t k = blockIdx.x;
+    const Span sp = cluster_span(off, k, n_points);
+    for (int64_t p = sp.lo + threadIdx.x; p < sp.lo + sp.n; p += kScoreBlock)
+        stage_point(theta, vd, p, cs32, v32, cs64);
+    if (threadIdx.x == 0) best_key[k] = 0;
+    __syncthreads();
+    ClusterId id;
+    id.out = k;
+    id.local = (uint32_t)k;
+    id.key0 = key0;
+    id.key1 = key1;
+    score_block<false>(sp, id, 0, n_hyp, pts, tau, kRowsMax, s_hyp, s_key, best_key, o.hyp_counts);
+    // The workgroup's own block key is the cluster's best (one block per
+    // cluster); the per-wave keys are still in LDS after score_block's barrier.
+    unsigned long long best = 0;
+#pragma unroll
+    for (int w = 0; w < kScoreBlock / kWave; ++w) best = s_key[w] > best ? s_key[w] : best;
+    refit_block(sp, id, uniform_u64(best), pts, tau, o, s_sum, s_cnt);
+}
+
 struct Batch {
     const int32_t *frame_off;  // [n_frames + 1]
     const uint64_t *seeds;     // [n_frames], device
@@ -1037,15 +1079,7 @@ __global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(
     for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) local[c] = 0;
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
-    if (p < n_points) {
-        const float t = theta[p], v = vd[p];
-        double s, c;
-        sincos((double)t, &s, &c);
-        const bool ok = isfinite(t) && isfinite(v);
-        cs32[p] = make_float2(ok ? (float)c : 0.0f, ok ? (float)s : 0.0f);
-        v32[p] = ok ? v : __builtin_inff();
-        cs64[p] = make_double2(c, s);
-    }
+    if (p < n_points) stage_point(theta, vd, p, cs32, v32, cs64);
     if (bits != nullptr && p < n_words) bits[p] = 0u;
     if (p < n_clusters) {
         best_key[p] = 0;
@@ -1413,6 +1447,20 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     return RV_OK;
 }
 
+// Frames small enough that launch latency dominates take the one-launch path
+// (small_frame_kernel): at most 256 hypotheses (one scoring block per cluster,
+// as on the three-kernel path), at most 65,536 points (each workgroup stages
+// its own cluster) and no frame-wide inlier mask (its words are shared by
+// neighbouring clusters and are cleared by the staging kernel).
+constexpr int64_t kSmallFrameMaxPoints = 1 << 16;
+constexpr int64_t kSmallFrameMaxClusters = 1 << 16;
+
+bool use_small_frame_path(int64_t n_clusters, int64_t n_points, int32_t n_hyp,
+                          const uint32_t *inlier_bits) {
+    return inlier_bits == nullptr && n_hyp <= kScoreBlock && n_points <= kSmallFrameMaxPoints &&
+           n_clusters <= kSmallFrameMaxClusters;
+}
+
 BatchArgs make_batch_args(const float *theta, const float *vd, const int32_t *cluster_offsets,
                           const int32_t *frame_offsets, const uint64_t *seeds, int64_t n_frames,
                           int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau,
@@ -1509,9 +1557,35 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     const int64_t n_words = inlier_bits != nullptr ? (n_points + 31) / 32 : 0;
     hipStream_t st = (hipStream_t)stream;
 
+    Outputs o;
+    o.vx = vx;
+    o.vy = vy;
+    o.heading = heading;
+    o.n_inliers = n_inliers;
+    o.status = status;
+    o.n_near = n_near_tau;
+    o.best = best_hyp;
+    o.hyp_counts = hyp_counts;
+    o.bits = inlier_bits;
+
     TimedCall tc;
     const bool timed = take_timed_call(tc);
     if (timed) (void)hipEventRecord(tc.ev[0], st);
+    if (use_small_frame_path(n_clusters, n_points, n_hyp, inlier_bits)) {
+        // One launch; its time counts as the scoring stage.
+        if (timed) (void)hipEventRecord(tc.ev[1], st);
+        hipLaunchKernelGGL(small_frame_kernel, dim3((unsigned)n_clusters), dim3(kScoreBlock), 0, st,
+                           theta, vd, cluster_offsets, n_points, n_hyp, key0, key1, pts, tau, cs32,
+                           v32, cs64, best_key, o);
+        if (timed) {
+            (void)hipEventRecord(tc.ev[2], st);
+            (void)hipEventRecord(tc.ev[3], st);
+            keep_timed_call(tc);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        return RV_OK;
+    }
     int64_t prep_items = n_points > n_words ? n_points : n_words;
     prep_items = prep_items > n_clusters ? prep_items : n_clusters;
     const int64_t prep_blocks = (prep_items + kPrepBlock - 1) / kPrepBlock + 1;  // + planner
@@ -1524,16 +1598,6 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
                        n_clusters, n_points, n_hyp, (int32_t)blocks_per_cluster, key0, key1,
                        pts, tau, best_key, hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
-    Outputs o;
-    o.vx = vx;
-    o.vy = vy;
-    o.heading = heading;
-    o.n_inliers = n_inliers;
-    o.status = status;
-    o.n_near = n_near_tau;
-    o.best = best_hyp;
-    o.hyp_counts = hyp_counts;
-    o.bits = inlier_bits;
     launch_refit(false, cluster_offsets, order, nullptr, n_clusters,
                  order != nullptr ? (const int64_t *)n_big : nullptr, n_points, key0, key1, pts,
                  best_key, tau, o, st);

@@ -255,3 +255,42 @@ def test_side_stream_call_keeps_its_workspace(rv):
         torch.cuda.synchronize()
         for k in ("vx", "vy", "heading", "n_inliers", "status"):
             assert torch.equal(torch.nan_to_num(got[k].float(), 7.0), torch.nan_to_num(ref[k].float(), 7.0)), (rep, k)
+
+
+def _small_frames():
+    """Frames that take the one-launch path when no inlier mask is requested."""
+    rng = np.random.default_rng(321)
+    small, H, tau = synth.make_workload("small")
+    yield "small-workload", small.theta, small.vd, small.offsets, H, tau, synth.ransac_seed("small")
+    for H in (1, 7, 64, 65, 256):
+        sizes = rng.integers(2, 301, size=40)
+        th, vd, off = _frame_from_clusters([_cluster(rng, int(n)) for n in sizes])
+        yield f"random-H{H}", th, vd, off, H, 0.15, 0x5A11 + H
+    sizes = [2, 3, 63, 64, 65, 1023, 1024, 1025, 2049, 3000]
+    th, vd, off = _frame_from_clusters([_cluster(rng, n, outlier_frac=0.3) for n in sizes])
+    yield "row-and-pass-boundaries", th, vd, off, 256, 0.15, 4242
+    good = _cluster(rng, 50)
+    nan_cl = _cluster(rng, 60)
+    nan_cl[0][[1, 5]] = np.nan
+    nan_cl[1][[7, 9]] = np.inf
+    same = (np.full(30, 0.25, np.float32), rng.uniform(-3, 3, 30).astype(np.float32))
+    th, vd, off = _frame_from_clusters([([], []), ([0.3], [2.0]), good, same, nan_cl,
+                                        ([0.0, 0.5], [1.0, 1.0])])
+    yield "edge-clusters", th, vd, off, 200, 0.15, 77
+    bad = off.copy()
+    bad[3] = bad[4] + 5  # inconsistent offsets for two clusters
+    yield "bad-offsets", th, vd, bad, 64, 0.15, 78
+
+
+def test_small_frame_path_matches_three_kernel_path(rv, oracle_mod):
+    """Without an inlier mask, small frames (<= 65,536 points, <= 256 hypotheses)
+    run as one fused launch; every output equals the three-kernel path's
+    (taken when the mask is requested) bitwise, and the oracle's by the protocol."""
+    for name, th, vd, off, H, tau, seed in _small_frames():
+        fused = parity.run_gpu(th, vd, off, H, tau, seed, debug=True, bits=False, label=f"{name}-fused")
+        three = parity.run_gpu(th, vd, off, H, tau, seed, debug=True, bits=True, label=f"{name}-3k")
+        for k in ("vx", "vy", "heading", "n_inliers", "status", "n_near_tau", "hyp_counts", "best_hyp"):
+            assert np.array_equal(fused[k], three[k], equal_nan=k in ("vx", "vy", "heading")), (name, k)
+        if name != "bad-offsets":
+            o = oracle_mod.estimate_velocity(th, vd, off, H, tau, seed, debug=True)
+            parity.report(f"{name}-fused", parity.check(th, vd, off, H, tau, seed, fused, o))
