@@ -334,8 +334,10 @@ const char *rv_last_error(void);
  * trials, refit).  rv_stage_times waits for the recorded events, writes
  * the summed milliseconds per stage (ms[0]: point staging and dispatch
  * planning, ms[1]: hypotheses and scoring, ms[2]: selection and refit) and the
- * number of calls into *n_calls, and clears the record.  Returns RV_OK or
- * RV_ERR_HIP.
+ * number of calls into *n_calls, and clears the record.  A single-frame call
+ * that takes the one-launch path for small frames (at most 65,536 points, at
+ * most 256 hypotheses, no inlier mask requested; same results) counts wholly as
+ * ms[1].  Returns RV_OK or RV_ERR_HIP.
  */
 int rv_stage_timing(int enable);
 int rv_stage_times(double *ms, int64_t *n_calls);
