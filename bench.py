@@ -52,11 +52,24 @@ WORKLOAD_TEXT["paper-sweep"] = (
 FRAME_WORKLOADS = ("dense", "small")
 
 
+def kernel_code_sha256(path: str) -> str:
+    """sha256 of a kernel source with its // comments and blank lines removed,
+    so that a committed profile stays valid across comment-only edits."""
+    import hashlib
+
+    lines = []
+    with open(path, encoding="utf-8") as f:
+        for line in f:
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def profiled_traffic(workload: str, kernel: str = "score_kernel"):
     """HBM bytes per scoring launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a copy of known size), or None
-    when there is none for this workload or the kernel source changed since."""
-    import hashlib
+    when there is none for this workload or the kernel code changed since."""
     import re
 
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
@@ -67,7 +80,7 @@ def profiled_traffic(workload: str, kernel: str = "score_kernel"):
     if not m:
         return None
     rec = json.loads(m.group(1))
-    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if rec.get("kernel_code_sha256") != kernel_code_sha256(src):
         return None
     return rec["hbm_bytes_per_launch"]
 
@@ -76,7 +89,6 @@ def profiled_valu_issue(workload: str):
     """Vector-instruction issue of score_kernel from the committed SQ counters
     (same kernel source only): instructions per SIMD per cycle at the clock the
     chip held, against 0.25 for back-to-back full-rate wave64 FMAs."""
-    import hashlib
     import re
 
     path = os.path.join(ROOT, "profiles", f"score_kernel_{workload}_counters.md")
@@ -88,7 +100,7 @@ def profiled_valu_issue(workload: str):
         return None
     rec = json.loads(m.group(1))
     sq = rec.get("sq")
-    if sq is None or rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if sq is None or rec.get("kernel_code_sha256") != kernel_code_sha256(src):
         return None
     simds, xcds = 1024, 8
     cycles = sq["GRBM_GUI_ACTIVE"] / xcds  # GRBM counts per XCD, summed over the 8

@@ -1,11 +1,12 @@
 // rv.hip -- gfx950 kernels and host entry points of the per-cluster RANSAC
 // velocity and heading estimator declared in include/rv.h.
 //
-// One call enqueues three kernels on the caller's stream:
+// A single-frame call enqueues three kernels on the caller's stream:
 //   prep    one thread per point: FP64 sincos of the azimuth; stages float32
-//           (cos, sin) and v_d for scoring and FP64 (cos, sin) for the solves; clears the optional frame-wide inlier bitmask and the
-//           per-cluster best keys.  Its last workgroup plans the dispatch
-//           order: clusters by decreasing size.
+//           (cos, sin) and v_d for scoring and FP64 (cos, sin) for the solves;
+//           clears the optional frame-wide inlier bitmask and the per-cluster
+//           best keys.  Its first workgroup plans the dispatch order: clusters
+//           by decreasing size.
 //   score   the hot loop.  Workgroup = (cluster, block of 256 hypotheses).
 //           Each thread draws one Philox4x32-10 seed pair and solves the 2x2
 //           system in FP64 (Sec. 3.1, Alg. 1: seeds, slope and intercept, as the
@@ -21,6 +22,11 @@
 //           1024 points or more: FP64 re-classification under the kept
 //           hypothesis, FP64 normal-equation sums in a fixed reduction tree,
 //           2x2 solve (Sec. 3.2, Eq. 7, Alg. 2) and atan2 heading (Eq. 8).
+// Small frames without an inlier mask take one launch (small_frame_kernel)
+// that runs the same three steps per cluster in one workgroup.  The batched
+// form stages, orders and describes the clusters of many frames, scores them
+// from per-XCD work queues in one persistent launch (optionally in the FP16
+// residual form) and refits them in one more launch.
 //
 // No floating-point atomics and fixed reduction orders: results are bitwise
 // reproducible run to run and independent of the other clusters in the frame.
