@@ -237,10 +237,11 @@ __global__ __launch_bounds__(kPaperBlock) void paper_score_kernel(
         const Line L = trial_line(theta + sp.lo, pts, n, (uint32_t)h, (uint32_t)k, key0, key1);
         int count = 0;
         if (L.valid) {
-            for (int p = 0; p < n; ++p) {
-                const double2 q = pts[p];
-                if (!__builtin_isnan(q.x) && within(L, q, th)) count += 1;
-            }
+            // Points are independent: unrolled and without a branch, several
+            // FP64 division chains overlap.  A point that takes no part is
+            // stored as (NaN, NaN); its distance is NaN and never passes.
+#pragma unroll 8
+            for (int p = 0; p < n; ++p) count += within(L, pts[p], th) ? 1 : 0;
             key = ((unsigned long long)count << 32) | (0xFFFFFFFFull - (uint32_t)h);
         }
         if (hyp_counts != nullptr) hyp_counts[k * n_hyp + h] = count;
