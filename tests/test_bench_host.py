@@ -1,0 +1,52 @@
+"""CPU: host-side logic of bench.py.
+
+* more than one GPU is refused with a message (this estimator runs on one GPU);
+* the kernel-code hash ignores comments and blank lines but not code;
+* a committed counter summary is read back only while the kernel code is the
+  code it was taken on.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_kernel_code_hash_ignores_comments_only(tmp_path):
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text("int f() {\n    return 1;  // one\n}\n")
+    b.write_text("// a header comment\n\nint f() {\n    return 1;\n}\n\n")
+    c.write_text("int f() {\n    return 2;\n}\n")
+    assert bench.kernel_code_sha256(str(a)) == bench.kernel_code_sha256(str(b))
+    assert bench.kernel_code_sha256(str(a)) != bench.kernel_code_sha256(str(c))
+
+
+def test_counter_summaries_are_read_back_only_for_their_code():
+    import json
+    import re
+
+    src = os.path.join(ROOT, "paper_2012_12618_amd", "csrc", "rv.hip")
+    path = os.path.join(ROOT, "profiles", "score_kernel_dense_counters.md")
+    if not os.path.exists(path):
+        pytest.skip("no committed counter summary")
+    rec = json.loads(re.search(r"```json\n(.*?)\n```", open(path).read(), re.S).group(1))
+    current = rec.get("kernel_code_sha256") == bench.kernel_code_sha256(src)
+    assert (bench.profiled_traffic("dense") is not None) == current
+    issue = bench.profiled_valu_issue("dense")
+    assert (issue is not None) == current
+    if current:
+        assert 0.0 < issue["valu_instructions_per_simd_cycle"] < 1.0
