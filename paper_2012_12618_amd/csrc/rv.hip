@@ -407,6 +407,8 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
 // 2^-8 A + 2^-18 (tau + M + 1), which also covers the float32 rounding of
 // tau + B_h.  A hypothesis with A >= 2^14 (or not finite) is not converted:
 // its FP16 row counts every finite point (threshold +inf), a valid upper bound.
+// (cos, sin) below 2^-14 in magnitude may lose their value in the dot product
+// if it flushes FP16 subnormals; that error, at most 2^-14 A, is inside 2^-8 A.
 // ---------------------------------------------------------------------------
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
@@ -419,12 +421,24 @@ constexpr float kFp16MaxOffset = 16384.0f;
 __device__ __forceinline__ float2 fp16_hypothesis(float hx, float hy, float rx, float ry,
                                                   float tau) {
     if (__builtin_isnan(hx) || __builtin_isnan(hy)) return make_float2(0.0f, 0.0f);
-    const float dx = hx - rx, dy = hy - ry;
+    float dx = hx - rx, dy = hy - ry;
     const float a = __builtin_fabsf(dx) + __builtin_fabsf(dy);
     if (!(a < kFp16MaxOffset)) return make_float2(0.0f, __builtin_inff());
     const float m = __builtin_fabsf(hx) + __builtin_fabsf(hy) + __builtin_fabsf(rx) +
                     __builtin_fabsf(ry);
-    const float band = a * 0x1p-8f + (tau + m + 1.0f) * 0x1p-18f;
+    // An offset component below the smallest normal FP16 value is sent as 0 and
+    // its magnitude (at most 2^-14 per point, |cos|, |sin| <= 1) joins the band,
+    // so the bound holds whether or not the dot product keeps FP16 subnormals.
+    float tiny = 0.0f;
+    if (__builtin_fabsf(dx) < 0x1p-14f) {
+        tiny += __builtin_fabsf(dx);
+        dx = 0.0f;
+    }
+    if (__builtin_fabsf(dy) < 0x1p-14f) {
+        tiny += __builtin_fabsf(dy);
+        dy = 0.0f;
+    }
+    const float band = a * 0x1p-8f + (tau + m + 1.0f) * 0x1p-18f + 2.0f * tiny;
     const half2_t nd = half2_t{(_Float16)(-dx), (_Float16)(-dy)};
     return make_float2(__builtin_bit_cast(float, nd), tau + band);
 }
