@@ -50,3 +50,22 @@ def test_counter_summaries_are_read_back_only_for_their_code():
     assert (issue is not None) == current
     if current:
         assert 0.0 < issue["valu_instructions_per_simd_cycle"] < 1.0
+
+
+def test_oracle_error_summary_per_cluster_bound():
+    import numpy as np
+
+    o_vx = np.array([10.0, -3.0, 0.5, 7.0])
+    o_vy = np.array([1.0, 2.0, -0.25, 7.0])
+    o_hd = np.arctan2(o_vy, o_vx)
+    vx = o_vx.astype(np.float32)
+    vy = o_vy.astype(np.float32)
+    vy[2] = np.float32(-0.25 + 1e-6)  # one result beyond float32 rounding
+    best = np.array([5, 6, 7, 8])
+    o_best = np.array([5, 6, 7, 9])  # the last cluster kept another hypothesis
+    e = bench.oracle_error_summary(vx, vy, np.arctan2(vy, vx).astype(np.float32), best,
+                                   o_vx, o_vy, o_hd, o_best)
+    assert e["clusters"] == 4 and e["same_hypothesis"] == 3
+    assert e["dv_within_float32_rounding"] == 2
+    assert abs(e["abs_dv_mps"]["max"] - 1e-6) < 1e-8
+    assert e["abs_dheading_rad"]["max"] < 1e-5
