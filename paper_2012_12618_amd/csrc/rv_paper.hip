@@ -6,15 +6,18 @@
 //   stats   one workgroup: per-cluster min-max normalisation of azimuth and
 //           Doppler onto [0, 1] (Alg. 1's normalize(); a zero span maps to 0),
 //           then the median absolute deviation of the normalised Doppler
-//           values (Eq. 5, read as the statistic the text names): two
-//           bitonic sorts of up to 4096 doubles in LDS.
+//           values (Eq. 5, read as the statistic the text names): two medians
+//           in LDS, by ranks for up to 256 points, else by bitonic sorts of
+//           up to 4096 doubles.
 //   score   one thread per (trial, cluster), the mapping of Alg. 1: the trial
 //           draws its seed pair from Philox4x32-10 exactly as the
 //           velocity-profile kernels do, fits the line through the two
 //           normalised seeds, and counts the points whose perpendicular
 //           distance (aa x + bb y + cc over sqrt(aa^2 + bb^2)) is at most the
-//           threshold; the block's best (count, lowest index) key is merged per
-//           cluster with a 64-bit atomic maximum.
+//           threshold (for each line, as one comparison of the numerator
+//           against the largest value that passes, found once per trial); the
+//           block's best (count, lowest index) key is merged per cluster with a
+//           64-bit atomic maximum.
 //   refit   one workgroup: re-classifies every point under the kept line,
 //           writes the inlier mask, and solves the normal equations of the
 //           velocity profile on the inliers; heading = atan2(vy, vx).
@@ -89,6 +92,30 @@ __device__ __forceinline__ double sorted_median(const double *s, int m) {
     return (m & 1) ? s[m / 2] : (s[m / 2 - 1] + s[m / 2]) / 2.0;
 }
 
+// The same median for P <= kPaperBlock without sorting: thread i ranks entry
+// s[i] against all P entries (how many are below it, how many not above it);
+// the entry whose rank range holds a middle position is that order statistic
+// (equal entries write the same value), and the two middle values are combined
+// as sorted_median combines them.  Called by the whole workgroup; the barrier
+// orders the writes of mid[] before its reads.
+__device__ double rank_median(const double *s, int P, int m, double *mid) {
+    const int q1 = m / 2, q0 = (m & 1) ? q1 : q1 - 1;
+    const int i = threadIdx.x;
+    if (i < P) {
+        const double a = s[i];
+        int below = 0, upto = 0;
+        for (int j = 0; j < P; ++j) {
+            const double b = s[j];
+            below += b < a ? 1 : 0;
+            upto += b <= a ? 1 : 0;
+        }
+        if (below <= q0 && q0 < upto) mid[0] = a;
+        if (below <= q1 && q1 < upto) mid[1] = a;
+    }
+    __syncthreads();
+    return (m & 1) ? mid[1] : (mid[0] + mid[1]) / 2.0;
+}
+
 // Spans of a cluster with 2 <= n <= RV_PAPER_MAX_POINTS points, the only ones
 // the score and refit kernels work on.
 __device__ __forceinline__ bool paper_cluster(const Span &sp) {
@@ -102,6 +129,7 @@ __global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
     __shared__ double s_sort[RV_PAPER_MAX_POINTS];
     __shared__ double s_red[4][kPaperWaves];
     __shared__ int s_cnt[kPaperWaves];
+    __shared__ double s_mid[2][2];
     const int64_t k = blockIdx.x;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     const Span sp = cluster_span(off, k, n_points);
@@ -167,8 +195,15 @@ __global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
     }
     __syncthreads();
     if (m_ok == 0) return;
-    bitonic_sort(s_sort, P);
-    const double med = sorted_median(s_sort, m_ok);
+    // Up to one entry per thread: ranks; above that: a bitonic sort.
+    const bool ranks = P <= kPaperBlock;
+    double med;
+    if (ranks) {
+        med = rank_median(s_sort, P, m_ok, s_mid[0]);
+    } else {
+        bitonic_sort(s_sort, P);
+        med = sorted_median(s_sort, m_ok);
+    }
     __syncthreads();
     for (int p = tid; p < P; p += kPaperBlock) {
         double d = __builtin_inf();
@@ -176,8 +211,14 @@ __global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
         s_sort[p] = d;
     }
     __syncthreads();
-    bitonic_sort(s_sort, P);
-    if (tid == 0) thresh[k] = sorted_median(s_sort, m_ok);
+    double mad;
+    if (ranks) {
+        mad = rank_median(s_sort, P, m_ok, s_mid[1]);
+    } else {
+        bitonic_sort(s_sort, P);
+        mad = sorted_median(s_sort, m_ok);
+    }
+    if (tid == 0) thresh[k] = mad;
 }
 
 // Line of a trial through its normalised seeds (Alg. 1: slope and intercept)
@@ -206,11 +247,46 @@ __device__ __forceinline__ Line trial_line(const float *__restrict__ t, const do
     return L;
 }
 
+// Numerator of Alg. 1's distance, aa x + bb y + cc with aa = -m, bb = 1 and
+// cc = -c, evaluated as written.
+__device__ __forceinline__ double dist_num(const Line &L, double2 p) {
+    const double aa = -L.m, bb = 1.0, cc = -L.c;
+    return (aa * p.x + bb * p.y) + cc;
+}
+
 // Alg. 1's inlier test of one point against a valid line.
 __device__ __forceinline__ bool within(const Line &L, double2 p, double th) {
-    const double aa = -L.m, bb = 1.0, cc = -L.c;
-    const double distn = (aa * p.x + bb * p.y) + cc;
-    return fabs(distn / L.distd) <= th;
+    return fabs(dist_num(L, p) / L.distd) <= th;
+}
+
+// The same test without a division per point.  For one line, the rounded
+// quotient |num| / distd is at most th exactly when |num| <= bound, the
+// largest double x >= 0 whose quotient x / distd rounds to at most th: a
+// correctly rounded quotient never decreases as x grows.  bound lies within a
+// few units in the last place of th * distd; it is found by bisection over the
+// bit patterns of the eight doubles around that product (non-negative doubles
+// order like their bit patterns), each step one division of the same kind as
+// the literal test's.  Returns false where that bracket does not hold (th = 0,
+// extreme magnitudes); the trial then runs the literal test.
+__device__ __forceinline__ bool pass_bound(double distd, double th, double &bound) {
+    if (!(distd >= 1.0) || !(distd < __builtin_inf()) || !(th > 0.0) || !(th < __builtin_inf()))
+        return false;
+    const double x0 = th * distd;
+    if (!(x0 > 0x1p-1000) || !(x0 < 0x1p1000)) return false;
+    long long lo = __builtin_bit_cast(long long, x0) - 4;
+    long long hi = lo + 8;
+    if (!(__builtin_bit_cast(double, lo) / distd <= th) ||
+        __builtin_bit_cast(double, hi) / distd <= th)
+        return false;
+    while (hi - lo > 1) {
+        const long long mid = lo + (hi - lo) / 2;
+        if (__builtin_bit_cast(double, mid) / distd <= th)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    bound = __builtin_bit_cast(double, lo);
+    return true;
 }
 
 // Block = (cluster, 256 trials); thread = one trial (Alg. 1's thread).
@@ -237,11 +313,17 @@ __global__ __launch_bounds__(kPaperBlock) void paper_score_kernel(
         const Line L = trial_line(theta + sp.lo, pts, n, (uint32_t)h, (uint32_t)k, key0, key1);
         int count = 0;
         if (L.valid) {
-            // Points are independent: unrolled and without a branch, several
-            // FP64 division chains overlap.  A point that takes no part is
-            // stored as (NaN, NaN); its distance is NaN and never passes.
+            // A point that takes no part is stored as (NaN, NaN); its distance
+            // is NaN and never passes.  Points are independent: the loops are
+            // unrolled and have no branch.
+            double bound;
+            if (pass_bound(L.distd, th, bound)) {
 #pragma unroll 8
-            for (int p = 0; p < n; ++p) count += within(L, pts[p], th) ? 1 : 0;
+                for (int p = 0; p < n; ++p) count += fabs(dist_num(L, pts[p])) <= bound ? 1 : 0;
+            } else {
+#pragma unroll 8
+                for (int p = 0; p < n; ++p) count += within(L, pts[p], th) ? 1 : 0;
+            }
             key = ((unsigned long long)count << 32) | (0xFFFFFFFFull - (uint32_t)h);
         }
         if (hyp_counts != nullptr) hyp_counts[k * n_hyp + h] = count;

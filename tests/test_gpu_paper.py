@@ -118,3 +118,32 @@ def test_hand_worked_example_and_edge_cases(rv, oracle_mod):
     bad = np.array([0, 5, 3, 9], np.int32)
     g = _run(rv, theta[:9], vd[:9], bad, 16, 1, "bad offsets")
     assert g["status"][1] == rv.RV_CLUSTER_BAD_OFFSETS
+
+
+def test_ties_sizes_around_the_rank_limit(rv, oracle_mod):
+    # Doppler values on a coarse grid (many equal normalised values, so the
+    # medians fall on ties), odd and even counts of usable points, non-finite
+    # points, a majority of equal values (threshold 0: every trial takes the
+    # literal test), and sizes on both sides of 256 points (ranks below,
+    # bitonic sorts above).
+    rng = np.random.default_rng(12)
+    sizes = [2, 3, 4, 5, 17, 64, 127, 128, 129, 200, 255, 256, 257, 300, 511, 1024]
+    thetas, vds = [], []
+    for i, n in enumerate(sizes):
+        th = rng.uniform(-1.0, 1.0, n).astype(np.float32)
+        vd = (np.round(rng.uniform(-6, 6, n) * 2) / 2).astype(np.float32)
+        if i % 3 == 1 and n > 4:
+            vd[: n // 2 + 1] = 1.5  # more than half equal: the MAD is 0
+        if i % 4 == 2 and n > 3:
+            vd[1] = np.nan
+            th[2] = np.inf
+        thetas.append(th)
+        vds.append(vd)
+    theta = np.concatenate(thetas)
+    vd = np.concatenate(vds)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    for H, seed in ((64, 21), (256, 22)):
+        g = _run(rv, theta, vd, off, H, seed, f"ties H={H}")
+        o = oracle_mod.estimate_velocity_paper(theta, vd, off, H, seed, debug=True)
+        _compare(g, o, off, H)
+        assert np.count_nonzero(o.thresh == 0.0) >= 3
