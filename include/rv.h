@@ -217,7 +217,13 @@ void rv_graph_destroy(rv_graph_t *graph);
  * device, nullable) receives each cluster's threshold.  Clusters of more than
  * RV_PAPER_MAX_POINTS points get RV_CLUSTER_TOO_LARGE.  The workspace must hold
  * rv_paper_workspace_bytes(n_clusters, n_points, n_hyp) bytes, 256-byte
- * aligned (16 B per point + 16 B per cluster).
+ * aligned (16 B per point + 16 B per cluster).  The normalisation is per
+ * cluster, so where offsets are not non-decreasing the clusters whose ranges
+ * overlap another's get unspecified results (the decreasing one still gets
+ * RV_CLUSTER_BAD_OFFSETS).  Without inlier_bits, frames of
+ * at most 65,536 points and 65,536 clusters with n_hyp <= 256 run as one
+ * launch with the same results bit for bit (for rv_stage_times it counts
+ * wholly as the scoring stage).
  */
 size_t rv_paper_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t n_hyp);
 int rv_estimate_velocity_paper(const float *theta, const float *vd, const int32_t *cluster_offsets,

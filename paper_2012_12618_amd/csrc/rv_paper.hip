@@ -21,6 +21,10 @@
 //   refit   one workgroup: re-classifies every point under the kept line,
 //           writes the inlier mask, and solves the normal equations of the
 //           velocity profile on the inliers; heading = atan2(vy, vx).
+// Each step is a device function.  Calls that ask for the frame-wide inlier
+// mask, or have more than 256 trials per cluster, or frames above 65,536
+// points or clusters, run them as three kernels; all others run them in one
+// kernel, a workgroup per cluster, with the same results bit for bit.
 //
 // Everything is FP64 and evaluated exactly as written (no contraction), so
 // counts, masks and thresholds are the same bits as a plain FP64 evaluation of
@@ -92,19 +96,20 @@ __device__ __forceinline__ double sorted_median(const double *s, int m) {
     return (m & 1) ? s[m / 2] : (s[m / 2 - 1] + s[m / 2]) / 2.0;
 }
 
-// The same median for P <= kPaperBlock without sorting: thread i ranks entry
-// s[i] against all P entries (how many are below it, how many not above it);
-// the entry whose rank range holds a middle position is that order statistic
-// (equal entries write the same value), and the two middle values are combined
-// as sorted_median combines them.  Called by the whole workgroup; the barrier
-// orders the writes of mid[] before its reads.
-__device__ double rank_median(const double *s, int P, int m, double *mid) {
+// The same median for n <= kPaperBlock entries without sorting (entries past
+// n are the +inf padding, never below a finite entry, so they are left out):
+// thread i ranks entry s[i] against all n (how many are below it, how many not
+// above it); the entry whose rank range holds a middle position is that order
+// statistic (equal entries write the same value), and the two middle values
+// are combined as sorted_median combines them.  Called by the whole workgroup;
+// the barrier orders the writes of mid[] before its reads.
+__device__ double rank_median(const double *s, int n, int m, double *mid) {
     const int q1 = m / 2, q0 = (m & 1) ? q1 : q1 - 1;
     const int i = threadIdx.x;
-    if (i < P) {
+    if (i < n) {
         const double a = s[i];
         int below = 0, upto = 0;
-        for (int j = 0; j < P; ++j) {
+        for (int j = 0; j < n; ++j) {
             const double b = s[j];
             below += b < a ? 1 : 0;
             upto += b <= a ? 1 : 0;
@@ -122,22 +127,24 @@ __device__ __forceinline__ bool paper_cluster(const Span &sp) {
     return sp.ok && sp.n >= 2 && sp.n <= RV_PAPER_MAX_POINTS;
 }
 
-__global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
-    const float *__restrict__ theta, const float *__restrict__ vd,
-    const int32_t *__restrict__ off, int64_t n_points, double2 *__restrict__ xy,
-    double *__restrict__ thresh, unsigned long long *__restrict__ best_key) {
-    __shared__ double s_sort[RV_PAPER_MAX_POINTS];
-    __shared__ double s_red[4][kPaperWaves];
-    __shared__ int s_cnt[kPaperWaves];
-    __shared__ double s_mid[2][2];
-    const int64_t k = blockIdx.x;
+// Workgroup LDS of the threshold step.
+struct StatsShared {
+    double sort[RV_PAPER_MAX_POINTS];
+    double red[4][kPaperWaves];
+    int cnt[kPaperWaves];
+    double mid[2][2];
+};
+
+// Threshold step of cluster k (whole workgroup; uniform early returns): the
+// normalised (x, y) of its points into xy, and its threshold into thresh[k],
+// NaN when the cluster takes no part or has no usable point.  Returns the
+// threshold in every thread.
+__device__ double paper_stats(const float *__restrict__ theta, const float *__restrict__ vd,
+                              Span sp, int64_t k, double2 *__restrict__ xy,
+                              double *__restrict__ thresh, StatsShared &sh) {
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const Span sp = cluster_span(off, k, n_points);
-    if (tid == 0) {
-        best_key[k] = 0;
-        thresh[k] = __builtin_nan("");
-    }
-    if (!paper_cluster(sp)) return;
+    if (tid == 0) thresh[k] = __builtin_nan("");
+    if (!paper_cluster(sp)) return __builtin_nan("");
     const int n = (int)sp.n;
     const float *t = theta + sp.lo, *v = vd + sp.lo;
 
@@ -158,24 +165,24 @@ __global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
     vmax = wave_max(vmax);
     m_ok = wave_sum_i(m_ok);
     if (lane == 0) {
-        s_red[0][wave] = tmin;
-        s_red[1][wave] = tmax;
-        s_red[2][wave] = vmin;
-        s_red[3][wave] = vmax;
-        s_cnt[wave] = m_ok;
+        sh.red[0][wave] = tmin;
+        sh.red[1][wave] = tmax;
+        sh.red[2][wave] = vmin;
+        sh.red[3][wave] = vmax;
+        sh.cnt[wave] = m_ok;
     }
     __syncthreads();
-    tmin = s_red[0][0];
-    tmax = s_red[1][0];
-    vmin = s_red[2][0];
-    vmax = s_red[3][0];
-    m_ok = s_cnt[0];
+    tmin = sh.red[0][0];
+    tmax = sh.red[1][0];
+    vmin = sh.red[2][0];
+    vmax = sh.red[3][0];
+    m_ok = sh.cnt[0];
     for (int w = 1; w < kPaperWaves; ++w) {
-        tmin = fmin(tmin, s_red[0][w]);
-        tmax = fmax(tmax, s_red[1][w]);
-        vmin = fmin(vmin, s_red[2][w]);
-        vmax = fmax(vmax, s_red[3][w]);
-        m_ok += s_cnt[w];
+        tmin = fmin(tmin, sh.red[0][w]);
+        tmax = fmax(tmax, sh.red[1][w]);
+        vmin = fmin(vmin, sh.red[2][w]);
+        vmax = fmax(vmax, sh.red[3][w]);
+        m_ok += sh.cnt[w];
     }
     const double tspan = tmax - tmin, vspan = vmax - vmin;
 
@@ -191,34 +198,45 @@ __global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
             y = ok ? unit_coord(v[p], vmin, vspan) : __builtin_inf();
             xy[sp.lo + p] = make_double2(x, ok ? y : __builtin_nan(""));
         }
-        s_sort[p] = y;
+        sh.sort[p] = y;
     }
     __syncthreads();
-    if (m_ok == 0) return;
+    if (m_ok == 0) return __builtin_nan("");
     // Up to one entry per thread: ranks; above that: a bitonic sort.
     const bool ranks = P <= kPaperBlock;
     double med;
     if (ranks) {
-        med = rank_median(s_sort, P, m_ok, s_mid[0]);
+        med = rank_median(sh.sort, n, m_ok, sh.mid[0]);
     } else {
-        bitonic_sort(s_sort, P);
-        med = sorted_median(s_sort, m_ok);
+        bitonic_sort(sh.sort, P);
+        med = sorted_median(sh.sort, m_ok);
     }
     __syncthreads();
     for (int p = tid; p < P; p += kPaperBlock) {
         double d = __builtin_inf();
         if (p < n && isfinite(t[p]) && isfinite(v[p])) d = fabs(unit_coord(v[p], vmin, vspan) - med);
-        s_sort[p] = d;
+        sh.sort[p] = d;
     }
     __syncthreads();
     double mad;
     if (ranks) {
-        mad = rank_median(s_sort, P, m_ok, s_mid[1]);
+        mad = rank_median(sh.sort, n, m_ok, sh.mid[1]);
     } else {
-        bitonic_sort(s_sort, P);
-        mad = sorted_median(s_sort, m_ok);
+        bitonic_sort(sh.sort, P);
+        mad = sorted_median(sh.sort, m_ok);
     }
     if (tid == 0) thresh[k] = mad;
+    return mad;
+}
+
+__global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd,
+    const int32_t *__restrict__ off, int64_t n_points, double2 *__restrict__ xy,
+    double *__restrict__ thresh, unsigned long long *__restrict__ best_key) {
+    __shared__ StatsShared sh;
+    const int64_t k = blockIdx.x;
+    if (threadIdx.x == 0) best_key[k] = 0;
+    (void)paper_stats(theta, vd, cluster_span(off, k, n_points), k, xy, thresh, sh);
 }
 
 // Line of a trial through its normalised seeds (Alg. 1: slope and intercept)
@@ -289,25 +307,21 @@ __device__ __forceinline__ bool pass_bound(double distd, double th, double &boun
     return true;
 }
 
-// Block = (cluster, 256 trials); thread = one trial (Alg. 1's thread).
-__global__ __launch_bounds__(kPaperBlock) void paper_score_kernel(
-    const float *__restrict__ theta, const int32_t *__restrict__ off, int64_t n_points,
-    int32_t n_hyp, int32_t blocks_per_cluster, uint32_t key0, uint32_t key1,
-    const double2 *__restrict__ xy, const double *__restrict__ thresh,
-    unsigned long long *__restrict__ best_key, int32_t *__restrict__ hyp_counts) {
-    __shared__ unsigned long long s_key[kPaperWaves];
-    const int64_t k = blockIdx.x / blocks_per_cluster;
-    const int b = (int)(blockIdx.x % blocks_per_cluster);
+// Trial h of cluster k in this thread (Alg. 1's thread) and the best (count,
+// lowest index) key over the workgroup's trials, returned in every thread
+// (0 when none is valid).  Whole workgroup; uniform early return.
+__device__ unsigned long long paper_score(const float *__restrict__ theta, Span sp, int64_t k,
+                                          int64_t h, int32_t n_hyp, uint32_t key0, uint32_t key1,
+                                          const double2 *__restrict__ xy, double th,
+                                          int32_t *__restrict__ hyp_counts,
+                                          unsigned long long *s_key) {
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const int64_t h = (int64_t)b * kPaperBlock + tid;
-    const Span sp = cluster_span(off, k, n_points);
     if (!paper_cluster(sp)) {
         if (hyp_counts != nullptr && h < n_hyp) hyp_counts[k * n_hyp + h] = 0;
-        return;
+        return 0;
     }
     const int n = (int)sp.n;
     const double2 *pts = xy + sp.lo;
-    const double th = thresh[k];
     unsigned long long key = 0;
     if (h < n_hyp) {
         const Line L = trial_line(theta + sp.lo, pts, n, (uint32_t)h, (uint32_t)k, key0, key1);
@@ -331,10 +345,25 @@ __global__ __launch_bounds__(kPaperBlock) void paper_score_kernel(
     key = wave_max_u64(key);
     if (lane == 0) s_key[wave] = key;
     __syncthreads();
-    if (tid == 0) {
-        for (int w = 1; w < kPaperWaves; ++w) key = s_key[w] > key ? s_key[w] : key;
-        if (key != 0) atomicMax(&best_key[k], key);
-    }
+    key = s_key[0];
+    for (int w = 1; w < kPaperWaves; ++w) key = s_key[w] > key ? s_key[w] : key;
+    return key;
+}
+
+// Block = (cluster, 256 trials); blocks of one cluster merge their keys with a
+// 64-bit atomic maximum, whose result does not depend on their order.
+__global__ __launch_bounds__(kPaperBlock) void paper_score_kernel(
+    const float *__restrict__ theta, const int32_t *__restrict__ off, int64_t n_points,
+    int32_t n_hyp, int32_t blocks_per_cluster, uint32_t key0, uint32_t key1,
+    const double2 *__restrict__ xy, const double *__restrict__ thresh,
+    unsigned long long *__restrict__ best_key, int32_t *__restrict__ hyp_counts) {
+    __shared__ unsigned long long s_key[kPaperWaves];
+    const int64_t k = blockIdx.x / blocks_per_cluster;
+    const int b = (int)(blockIdx.x % blocks_per_cluster);
+    const int64_t h = (int64_t)b * kPaperBlock + threadIdx.x;
+    const unsigned long long key = paper_score(theta, cluster_span(off, k, n_points), k, h, n_hyp,
+                                               key0, key1, xy, thresh[k], hyp_counts, s_key);
+    if (threadIdx.x == 0 && key != 0) atomicMax(&best_key[k], key);
 }
 
 struct PaperOutputs {
@@ -355,23 +384,19 @@ __device__ __forceinline__ void paper_failed(const PaperOutputs &o, int64_t k, u
     if (o.best) o.best[k] = -1;
 }
 
-__global__ __launch_bounds__(kPaperBlock) void paper_refit_kernel(
-    const float *__restrict__ theta, const float *__restrict__ vd, const int32_t *__restrict__ off,
-    int64_t n_points, uint32_t key0, uint32_t key1, const double2 *__restrict__ xy,
-    const double *__restrict__ thresh, const unsigned long long *__restrict__ best_key,
-    PaperOutputs o) {
-    __shared__ double s_sum[kPaperWaves][5];
-    __shared__ int s_cnt[kPaperWaves];
-    const int64_t k = blockIdx.x;
+// Refit of cluster k under its kept trial `best` (0: none valid) with
+// threshold th (whole workgroup; uniform early returns).
+__device__ void paper_refit(const float *__restrict__ theta, const float *__restrict__ vd, Span sp,
+                            int64_t k, uint32_t key0, uint32_t key1, const double2 *__restrict__ xy,
+                            double th, unsigned long long best, const PaperOutputs &o,
+                            double (*s_sum)[5], int *s_cnt) {
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-    const Span sp = cluster_span(off, k, n_points);
     if (!sp.ok || sp.n < 2 || sp.n > RV_PAPER_MAX_POINTS) {
         if (tid == 0)
             paper_failed(o, k, !sp.ok ? RV_CLUSTER_BAD_OFFSETS
                                       : (sp.n < 2 ? RV_CLUSTER_TOO_FEW_POINTS : RV_CLUSTER_TOO_LARGE));
         return;
     }
-    const unsigned long long best = best_key[k];
     if (best == 0) {
         if (tid == 0) paper_failed(o, k, RV_CLUSTER_ALL_DEGENERATE);
         return;
@@ -380,7 +405,6 @@ __global__ __launch_bounds__(kPaperBlock) void paper_refit_kernel(
     const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
     const double2 *pts = xy + sp.lo;
     const Line L = trial_line(theta + sp.lo, pts, n, hbest, (uint32_t)k, key0, key1);
-    const double th = thresh[k];
     const int64_t end = sp.lo + sp.n;
     double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
     int n_in = 0;
@@ -462,6 +486,41 @@ __global__ __launch_bounds__(kPaperBlock) void paper_refit_kernel(
     o.status[k] = RV_CLUSTER_OK;
 }
 
+__global__ __launch_bounds__(kPaperBlock) void paper_refit_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd, const int32_t *__restrict__ off,
+    int64_t n_points, uint32_t key0, uint32_t key1, const double2 *__restrict__ xy,
+    const double *__restrict__ thresh, const unsigned long long *__restrict__ best_key,
+    PaperOutputs o) {
+    __shared__ double s_sum[kPaperWaves][5];
+    __shared__ int s_cnt[kPaperWaves];
+    const int64_t k = blockIdx.x;
+    paper_refit(theta, vd, cluster_span(off, k, n_points), k, key0, key1, xy, thresh[k],
+                best_key[k], o, s_sum, s_cnt);
+}
+
+// Frames whose clusters each take one workgroup of trials (at most 256), with
+// no frame-wide inlier mask requested (its words are shared by neighbouring
+// clusters): one launch, a workgroup per cluster, running the threshold step,
+// the trials and the refit with the same device functions as the three
+// kernels, so every output is theirs bit for bit.  A workgroup reads back only
+// the normalised points it wrote itself, after a workgroup barrier.
+__global__ __launch_bounds__(kPaperBlock) void paper_frame_kernel(
+    const float *__restrict__ theta, const float *__restrict__ vd, const int32_t *__restrict__ off,
+    int64_t n_points, int32_t n_hyp, uint32_t key0, uint32_t key1, double2 *__restrict__ xy,
+    double *__restrict__ thresh, int32_t *__restrict__ hyp_counts, PaperOutputs o) {
+    __shared__ StatsShared sh;
+    __shared__ unsigned long long s_key[kPaperWaves];
+    __shared__ double s_sum[kPaperWaves][5];
+    __shared__ int s_cnt[kPaperWaves];
+    const int64_t k = blockIdx.x;
+    const Span sp = cluster_span(off, k, n_points);
+    const double th = paper_stats(theta, vd, sp, k, xy, thresh, sh);
+    __syncthreads();
+    const unsigned long long best = paper_score(theta, sp, k, threadIdx.x, n_hyp, key0, key1, xy,
+                                                th, hyp_counts, s_key);
+    paper_refit(theta, vd, sp, k, key0, key1, xy, th, best, o, s_sum, s_cnt);
+}
+
 __global__ __launch_bounds__(kPaperBlock) void paper_clear_bits_kernel(uint32_t *__restrict__ bits,
                                                                       int64_t n_words) {
     const int64_t i = (int64_t)blockIdx.x * kPaperBlock + threadIdx.x;
@@ -469,6 +528,10 @@ __global__ __launch_bounds__(kPaperBlock) void paper_clear_bits_kernel(uint32_t 
 }
 
 constexpr size_t kPaperAlign = 256;
+// Frames of at most this many points and clusters take the one-launch path
+// (when no inlier mask is requested and n_hyp <= 256).
+constexpr int64_t kPaperFrameMaxPoints = 1 << 16;
+constexpr int64_t kPaperFrameMaxClusters = 1 << 16;
 
 size_t paper_align(size_t x) { return (x + kPaperAlign - 1) / kPaperAlign * kPaperAlign; }
 
@@ -529,10 +592,34 @@ int rv_estimate_velocity_paper(const float *theta, const float *vd, const int32_
     unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
     const uint32_t key0 = (uint32_t)(seed & 0xFFFFFFFFu), key1 = (uint32_t)(seed >> 32);
     hipStream_t st = (hipStream_t)stream;
-    // Stage events (rv_stage_timing): stats and mask clearing, scoring, refit.
+    PaperOutputs o;
+    o.vx = vx;
+    o.vy = vy;
+    o.heading = heading;
+    o.n_inliers = n_inliers;
+    o.status = status;
+    o.best = best_hyp;
+    o.bits = inlier_bits;
+    // Stage events (rv_stage_timing): stats and mask clearing, scoring, refit;
+    // the one-launch path counts wholly as scoring.
     TimedCall tc;
     const bool timed = take_timed_call(tc);
     if (timed) (void)hipEventRecord(tc.ev[0], st);
+    if (inlier_bits == nullptr && n_hyp <= kPaperBlock && n_points <= kPaperFrameMaxPoints &&
+        n_clusters <= kPaperFrameMaxClusters) {
+        if (timed) (void)hipEventRecord(tc.ev[1], st);
+        hipLaunchKernelGGL(paper_frame_kernel, dim3((unsigned)n_clusters), dim3(kPaperBlock), 0, st,
+                           theta, vd, cluster_offsets, n_points, n_hyp, key0, key1, xy, th,
+                           hyp_counts, o);
+        if (timed) {
+            (void)hipEventRecord(tc.ev[2], st);
+            (void)hipEventRecord(tc.ev[3], st);
+            keep_timed_call(tc);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+        return RV_OK;
+    }
     if (inlier_bits != nullptr) {
         const int64_t n_words = (n_points + 31) / 32;
         if (n_words > 0)
@@ -547,14 +634,6 @@ int rv_estimate_velocity_paper(const float *theta, const float *vd, const int32_
                        st, theta, cluster_offsets, n_points, n_hyp, (int32_t)bpc, key0, key1,
                        (const double2 *)xy, (const double *)th, best_key, hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
-    PaperOutputs o;
-    o.vx = vx;
-    o.vy = vy;
-    o.heading = heading;
-    o.n_inliers = n_inliers;
-    o.status = status;
-    o.best = best_hyp;
-    o.bits = inlier_bits;
     hipLaunchKernelGGL(paper_refit_kernel, dim3((unsigned)n_clusters), dim3(kPaperBlock), 0, st,
                        theta, vd, cluster_offsets, n_points, key0, key1, (const double2 *)xy,
                        (const double *)th, (const unsigned long long *)best_key, o);
