@@ -684,6 +684,77 @@ __device__ __forceinline__ void write_failed(const Outputs &o, int64_t k, uint8_
     if (o.best) o.best[k] = -1;
 }
 
+// FP64 sums of a refit, per lane.
+struct RefitSums {
+    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
+    int n_in = 0, n_near = 0;
+};
+
+// Re-classification of one 64-aligned block of points [p0, p0 + 64) under h*
+// (one wave, wave-uniform call): lane point p = p0 + lane counts when it lies
+// in [lo, end) and its v_d is finite (+inf marks a non-finite point); the
+// block's ballot fills two words of the frame-wide mask.  v and cs are loaded
+// by the caller, so that the loads of several blocks are in flight together.
+__device__ __forceinline__ void refit_points(int64_t p0, bool in_range, float v, double2 cs,
+                                             const Hypothesis &hy, double dtau, RefitSums &a,
+                                             const Outputs &o, int lane) {
+    bool inlier = false;
+    if (in_range && isfinite(v)) {
+        const double c = cs.x, s = cs.y, dv = v;
+        const double res = fabs(dv - hy.vx * c - hy.vy * s);
+        a.n_near += fabs(res - dtau) <= RV_NEAR_TAU_WINDOW ? 1 : 0;
+        if (res < dtau) {
+            inlier = true;
+            a.n_in += 1;
+            a.scc += c * c;
+            a.scs += c * s;
+            a.sss += s * s;
+            a.scv += c * dv;
+            a.ssv += s * dv;
+        }
+    }
+    if (o.bits != nullptr) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(inlier);
+        if (lane == 0) {
+            const uint32_t w0 = (uint32_t)m, w1 = (uint32_t)(m >> 32);
+            if (w0) atomicOr(&o.bits[p0 >> 5], w0);
+            if (w1) atomicOr(&o.bits[(p0 >> 5) + 1], w1);
+        }
+    }
+}
+
+// All points of a cluster under h*, 64-aligned blocks from first_block in
+// steps of `stride`, kRefitUnroll blocks per iteration: the loads of all of
+// them are issued (from a clamped, always valid index) before any block is
+// used.  Each lane visits its points in the same order as one block per
+// iteration, so the sums are the same.
+constexpr int kRefitUnroll = 4;
+
+__device__ __forceinline__ RefitSums refit_sweep(Span sp, int64_t first_block, int64_t stride,
+                                                 const Points &pts, const Hypothesis &hy,
+                                                 double dtau, const Outputs &o, int lane) {
+    RefitSums a;
+    const int64_t end = sp.lo + sp.n;
+    for (int64_t p0 = first_block; p0 < end; p0 += kRefitUnroll * stride) {
+        float v[kRefitUnroll];
+        double2 cs[kRefitUnroll];
+        bool in[kRefitUnroll];
+#pragma unroll
+        for (int u = 0; u < kRefitUnroll; ++u) {
+            const int64_t p = p0 + u * stride + lane;
+            in[u] = p >= sp.lo && p < end;
+            const int64_t q = in[u] ? p : sp.lo;
+            v[u] = pts.v32[q];
+            cs[u] = pts.cs64[q];
+        }
+#pragma unroll
+        for (int u = 0; u < kRefitUnroll; ++u)
+            if (p0 + u * stride < end)
+                refit_points(p0 + u * stride, in[u], v[u], cs[u], hy, dtau, a, o, lane);
+    }
+    return a;
+}
+
 // Refit of one cluster by one workgroup of kRefitBlock threads: the kept
 // hypothesis (from its best key), FP64 re-classification of every point under
 // it, least-squares refit on its inliers (Sec. 3.2, Eq. 7, Alg. 2: normal
@@ -708,42 +779,12 @@ __device__ __forceinline__ void refit_block(Span sp, ClusterId id, unsigned long
     const Hypothesis hy = make_hypothesis(pts, sp, hbest, id.local, id.key0, id.key1);
     const double dtau = tau;
 
-    // Threads walk 64-aligned global blocks so one wave ballot maps onto two
+    // Waves walk 64-aligned global blocks so one wave ballot maps onto two
     // words of the frame-wide bitmask.
-    const int64_t end = sp.lo + sp.n;
-    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
-    int n_in = 0, n_near = 0;
-    for (int64_t p0 = (sp.lo & ~(int64_t)(kWave - 1)) + (int64_t)wave * kWave; p0 < end;
-         p0 += kRefitBlock) {
-        const int64_t p = p0 + lane;
-        bool inlier = false;
-        if (p >= sp.lo && p < end) {
-            const float v = pts.v32[p];  // +inf marks a non-finite point
-            if (isfinite(v)) {
-                const double2 cs = pts.cs64[p];
-                const double c = cs.x, s = cs.y, dv = v;
-                const double res = fabs(dv - hy.vx * c - hy.vy * s);
-                n_near += fabs(res - dtau) <= RV_NEAR_TAU_WINDOW ? 1 : 0;
-                if (res < dtau) {
-                    inlier = true;
-                    n_in += 1;
-                    scc += c * c;
-                    scs += c * s;
-                    sss += s * s;
-                    scv += c * dv;
-                    ssv += s * dv;
-                }
-            }
-        }
-        if (o.bits != nullptr) {
-            const uint64_t m = __builtin_amdgcn_ballot_w64(inlier);
-            if (lane == 0) {
-                const uint32_t w0 = (uint32_t)m, w1 = (uint32_t)(m >> 32);
-                if (w0) atomicOr(&o.bits[p0 >> 5], w0);
-                if (w1) atomicOr(&o.bits[(p0 >> 5) + 1], w1);
-            }
-        }
-    }
+    const RefitSums a = refit_sweep(sp, (sp.lo & ~(int64_t)(kWave - 1)) + (int64_t)wave * kWave,
+                                    kRefitBlock, pts, hy, dtau, o, lane);
+    double scc = a.scc, scs = a.scs, sss = a.sss, scv = a.scv, ssv = a.ssv;
+    int n_in = a.n_in, n_near = a.n_near;
     scc = wave_sum(scc);
     scs = wave_sum(scs);
     sss = wave_sum(sss);
@@ -822,39 +863,9 @@ __device__ __forceinline__ void refit_wave(Span sp, ClusterId id, unsigned long 
 
     // 64-aligned global blocks of points, so one ballot maps onto two words of
     // the frame-wide bitmask.
-    const int64_t end = sp.lo + sp.n;
-    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
-    int n_in = 0, n_near = 0;
-    for (int64_t p0 = sp.lo & ~(int64_t)(kWave - 1); p0 < end; p0 += kWave) {
-        const int64_t p = p0 + lane;
-        bool inlier = false;
-        if (p >= sp.lo && p < end) {
-            const float v = pts.v32[p];  // +inf marks a non-finite point
-            if (isfinite(v)) {
-                const double2 cs = pts.cs64[p];
-                const double c = cs.x, s = cs.y, dv = v;
-                const double res = fabs(dv - hy.vx * c - hy.vy * s);
-                n_near += fabs(res - dtau) <= RV_NEAR_TAU_WINDOW ? 1 : 0;
-                if (res < dtau) {
-                    inlier = true;
-                    n_in += 1;
-                    scc += c * c;
-                    scs += c * s;
-                    sss += s * s;
-                    scv += c * dv;
-                    ssv += s * dv;
-                }
-            }
-        }
-        if (o.bits != nullptr) {
-            const uint64_t m = __builtin_amdgcn_ballot_w64(inlier);
-            if (lane == 0) {
-                const uint32_t w0 = (uint32_t)m, w1 = (uint32_t)(m >> 32);
-                if (w0) atomicOr(&o.bits[p0 >> 5], w0);
-                if (w1) atomicOr(&o.bits[(p0 >> 5) + 1], w1);
-            }
-        }
-    }
+    const RefitSums a = refit_sweep(sp, sp.lo & ~(int64_t)(kWave - 1), kWave, pts, hy, dtau, o, lane);
+    double scc = a.scc, scs = a.scs, sss = a.sss, scv = a.scv, ssv = a.ssv;
+    int n_in = a.n_in, n_near = a.n_near;
     scc = wave_sum(scc);
     scs = wave_sum(scs);
     sss = wave_sum(sss);
