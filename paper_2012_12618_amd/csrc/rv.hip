@@ -128,20 +128,21 @@ __device__ __forceinline__ Hypothesis make_hypothesis(const Points &pts, Span sp
     uint32_t i, j;
     seed_pair(u.x, u.y, (uint32_t)sp.n, i, j);
     const int64_t pi = sp.lo + i, pj = sp.lo + j;
+    // No branch before the solve: all six loads are in flight together, and
+    // an invalid pair's solve (possibly inf or NaN) is replaced by NaN.
     const float vi = pts.v32[pi], vj = pts.v32[pj];
-    Hypothesis hy;
-    hy.valid = isfinite(vi) && isfinite(vj) &&
-               fabs((double)pts.theta[pj] - (double)pts.theta[pi]) >= RV_MIN_SEED_SEPARATION;
-    if (!hy.valid) {
-        hy.vx = hy.vy = __builtin_nan("");
-        return hy;
-    }
+    const float ti = pts.theta[pi], tj = pts.theta[pj];
     const double2 ai = pts.cs64[pi], bj = pts.cs64[pj];
+    Hypothesis hy;
+    hy.valid = isfinite(vi) & isfinite(vj) &
+               (fabs((double)tj - (double)ti) >= RV_MIN_SEED_SEPARATION);
     const double ci = ai.x, si = ai.y, cj = bj.x, sj = bj.y;
     const double dvi = vi, dvj = vj;
     const double inv_det = 1.0 / (ci * sj - si * cj);
-    hy.vx = (dvi * sj - dvj * si) * inv_det;
-    hy.vy = (ci * dvj - cj * dvi) * inv_det;
+    const double vx = (dvi * sj - dvj * si) * inv_det;
+    const double vy = (ci * dvj - cj * dvi) * inv_det;
+    hy.vx = hy.valid ? vx : __builtin_nan("");
+    hy.vy = hy.valid ? vy : __builtin_nan("");
     return hy;
 }
 
