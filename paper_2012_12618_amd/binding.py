@@ -443,12 +443,27 @@ def rv_paper_workspace_bytes(n_clusters: int, n_points: int, n_hyp: int) -> int:
     return int(load_library().rv_paper_workspace_bytes(int(n_clusters), int(n_points), int(n_hyp)))
 
 
+def allocate_paper_outputs(n_clusters: int, n_points: int, n_hyp: int, device, *,
+                           want_bits: bool = False, debug: bool = False) -> dict:
+    """Output tensors for rv_estimate_velocity_paper (plus its workspace)."""
+    out = allocate_outputs(n_clusters, n_points, n_hyp, device, want_near=False,
+                           want_bits=want_bits, debug=debug)
+    dev = torch.device(device)
+    out["thresh"] = torch.empty(n_clusters, dtype=torch.float64, device=dev)
+    out["workspace"] = torch.empty(max(rv_paper_workspace_bytes(n_clusters, n_points, n_hyp), 1),
+                                   dtype=torch.uint8, device=dev)
+    return out
+
+
 def rv_estimate_velocity_paper(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
                                n_hyp: int, seed: int, *, want_bits: bool = False,
-                               debug: bool = False, stream=None) -> dict:
+                               debug: bool = False, out: dict | None = None,
+                               stream=None) -> dict:
     """Paper-literal inlier kernel (normalised line fit, MAD threshold, <= test)
     and the least-squares refit; outputs as rv_estimate_velocity plus ``thresh``
-    (float64 per cluster)."""
+    (float64 per cluster).  Outputs and workspace are allocated with torch
+    unless ``out`` (from ``allocate_paper_outputs``) is given; the frame-wide
+    mask and the debug outputs are written when ``out`` holds them."""
     lib = load_library()
     device = theta.device
     if device.type != "cuda":
@@ -456,12 +471,12 @@ def rv_estimate_velocity_paper(theta: torch.Tensor, vd: torch.Tensor, offsets: t
     n_points, n_clusters = int(theta.numel()), int(offsets.numel()) - 1
     if n_clusters < 0 or int(vd.numel()) != n_points:
         raise ValueError("offsets needs n_clusters + 1 entries; theta and vd must match")
-    out = allocate_outputs(n_clusters, n_points, n_hyp, device, want_near=False,
-                           want_bits=want_bits, debug=debug)
-    out.pop("workspace")
-    out["thresh"] = torch.empty(n_clusters, dtype=torch.float64, device=device)
-    ws = torch.empty(max(rv_paper_workspace_bytes(n_clusters, n_points, n_hyp), 1),
-                     dtype=torch.uint8, device=device)
+    owned = out is None
+    if owned:
+        out = allocate_paper_outputs(n_clusters, n_points, n_hyp, device, want_bits=want_bits,
+                                     debug=debug)
+    out = dict(out)
+    ws = out.pop("workspace")
     if stream is None:
         stream = torch.cuda.current_stream(device)
     _check(lib.rv_estimate_velocity_paper(
@@ -477,7 +492,8 @@ def rv_estimate_velocity_paper(theta: torch.Tensor, vd: torch.Tensor, offsets: t
         _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
         _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
         ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream)))
-    _used_on(stream, list(out.values()) + [ws])
+    if owned:
+        _used_on(stream, list(out.values()) + [ws])
     return out
 
 

@@ -136,27 +136,39 @@ struct StatsShared {
 };
 
 // Threshold step of cluster k (whole workgroup; uniform early returns): the
-// normalised (x, y) of its points into xy, and its threshold into thresh[k],
+// normalised (x, y) of its points into xy (and into s_xy, when given, for
+// clusters of at most kPaperBlock points), and its threshold into thresh[k],
 // NaN when the cluster takes no part or has no usable point.  Returns the
 // threshold in every thread.
 __device__ double paper_stats(const float *__restrict__ theta, const float *__restrict__ vd,
                               Span sp, int64_t k, double2 *__restrict__ xy,
-                              double *__restrict__ thresh, StatsShared &sh) {
+                              double *__restrict__ thresh, StatsShared &sh, double2 *s_xy) {
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
     if (tid == 0) thresh[k] = __builtin_nan("");
     if (!paper_cluster(sp)) return __builtin_nan("");
     const int n = (int)sp.n;
     const float *t = theta + sp.lo, *v = vd + sp.lo;
+    // With at most one point per thread, each thread keeps its point and its
+    // normalised Doppler value in registers across the steps (every loop
+    // below then runs once, at p = tid).
+    const bool one = n <= kPaperBlock;
+    float t_own = 0.0f, v_own = 0.0f;
+    double y_own = 0.0;
+    if (one && tid < n) {
+        t_own = t[tid];
+        v_own = v[tid];
+    }
 
     double tmin = __builtin_inf(), tmax = -__builtin_inf();
     double vmin = __builtin_inf(), vmax = -__builtin_inf();
     int m_ok = 0;
     for (int p = tid; p < n; p += kPaperBlock) {
-        if (!(isfinite(t[p]) && isfinite(v[p]))) continue;
-        tmin = fmin(tmin, (double)t[p]);
-        tmax = fmax(tmax, (double)t[p]);
-        vmin = fmin(vmin, (double)v[p]);
-        vmax = fmax(vmax, (double)v[p]);
+        const float tp = one ? t_own : t[p], vp = one ? v_own : v[p];
+        if (!(isfinite(tp) && isfinite(vp))) continue;
+        tmin = fmin(tmin, (double)tp);
+        tmax = fmax(tmax, (double)tp);
+        vmin = fmin(vmin, (double)vp);
+        vmax = fmax(vmax, (double)vp);
         m_ok += 1;
     }
     tmin = wave_min(tmin);
@@ -193,11 +205,15 @@ __device__ double paper_stats(const float *__restrict__ theta, const float *__re
     for (int p = tid; p < P; p += kPaperBlock) {
         double y = __builtin_inf();
         if (p < n) {
-            const bool ok = isfinite(t[p]) && isfinite(v[p]);
-            const double x = ok ? unit_coord(t[p], tmin, tspan) : __builtin_nan("");
-            y = ok ? unit_coord(v[p], vmin, vspan) : __builtin_inf();
-            xy[sp.lo + p] = make_double2(x, ok ? y : __builtin_nan(""));
+            const float tp = one ? t_own : t[p], vp = one ? v_own : v[p];
+            const bool ok = isfinite(tp) && isfinite(vp);
+            const double x = ok ? unit_coord(tp, tmin, tspan) : __builtin_nan("");
+            y = ok ? unit_coord(vp, vmin, vspan) : __builtin_inf();
+            const double2 q = make_double2(x, ok ? y : __builtin_nan(""));
+            xy[sp.lo + p] = q;
+            if (one && s_xy != nullptr) s_xy[p] = q;
         }
+        if (one) y_own = y;
         sh.sort[p] = y;
     }
     __syncthreads();
@@ -214,7 +230,12 @@ __device__ double paper_stats(const float *__restrict__ theta, const float *__re
     __syncthreads();
     for (int p = tid; p < P; p += kPaperBlock) {
         double d = __builtin_inf();
-        if (p < n && isfinite(t[p]) && isfinite(v[p])) d = fabs(unit_coord(v[p], vmin, vspan) - med);
+        if (one) {
+            // y_own is +inf exactly for a point that takes no part.
+            if (p < n && y_own < __builtin_inf()) d = fabs(y_own - med);
+        } else if (p < n && isfinite(t[p]) && isfinite(v[p])) {
+            d = fabs(unit_coord(v[p], vmin, vspan) - med);
+        }
         sh.sort[p] = d;
     }
     __syncthreads();
@@ -236,7 +257,7 @@ __global__ __launch_bounds__(kPaperBlock) void paper_stats_kernel(
     __shared__ StatsShared sh;
     const int64_t k = blockIdx.x;
     if (threadIdx.x == 0) best_key[k] = 0;
-    (void)paper_stats(theta, vd, cluster_span(off, k, n_points), k, xy, thresh, sh);
+    (void)paper_stats(theta, vd, cluster_span(off, k, n_points), k, xy, thresh, sh, nullptr);
 }
 
 // Line of a trial through its normalised seeds (Alg. 1: slope and intercept)
@@ -312,7 +333,7 @@ __device__ __forceinline__ bool pass_bound(double distd, double th, double &boun
 // (0 when none is valid).  Whole workgroup; uniform early return.
 __device__ unsigned long long paper_score(const float *__restrict__ theta, Span sp, int64_t k,
                                           int64_t h, int32_t n_hyp, uint32_t key0, uint32_t key1,
-                                          const double2 *__restrict__ xy, double th,
+                                          const double2 *__restrict__ pts, double th,
                                           int32_t *__restrict__ hyp_counts,
                                           unsigned long long *s_key) {
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
@@ -321,7 +342,6 @@ __device__ unsigned long long paper_score(const float *__restrict__ theta, Span 
         return 0;
     }
     const int n = (int)sp.n;
-    const double2 *pts = xy + sp.lo;
     unsigned long long key = 0;
     if (h < n_hyp) {
         const Line L = trial_line(theta + sp.lo, pts, n, (uint32_t)h, (uint32_t)k, key0, key1);
@@ -361,8 +381,10 @@ __global__ __launch_bounds__(kPaperBlock) void paper_score_kernel(
     const int64_t k = blockIdx.x / blocks_per_cluster;
     const int b = (int)(blockIdx.x % blocks_per_cluster);
     const int64_t h = (int64_t)b * kPaperBlock + threadIdx.x;
-    const unsigned long long key = paper_score(theta, cluster_span(off, k, n_points), k, h, n_hyp,
-                                               key0, key1, xy, thresh[k], hyp_counts, s_key);
+    const Span sp = cluster_span(off, k, n_points);
+    const double2 *pts = paper_cluster(sp) ? xy + sp.lo : xy;
+    const unsigned long long key =
+        paper_score(theta, sp, k, h, n_hyp, key0, key1, pts, thresh[k], hyp_counts, s_key);
     if (threadIdx.x == 0 && key != 0) atomicMax(&best_key[k], key);
 }
 
@@ -509,15 +531,22 @@ __global__ __launch_bounds__(kPaperBlock) void paper_frame_kernel(
     int64_t n_points, int32_t n_hyp, uint32_t key0, uint32_t key1, double2 *__restrict__ xy,
     double *__restrict__ thresh, int32_t *__restrict__ hyp_counts, PaperOutputs o) {
     __shared__ StatsShared sh;
+    __shared__ double2 s_xy[kPaperBlock];  // normalised points of clusters of <= 256 points
     __shared__ unsigned long long s_key[kPaperWaves];
     __shared__ double s_sum[kPaperWaves][5];
     __shared__ int s_cnt[kPaperWaves];
     const int64_t k = blockIdx.x;
     const Span sp = cluster_span(off, k, n_points);
-    const double th = paper_stats(theta, vd, sp, k, xy, thresh, sh);
+    const double th = paper_stats(theta, vd, sp, k, xy, thresh, sh, s_xy);
     __syncthreads();
-    const unsigned long long best = paper_score(theta, sp, k, threadIdx.x, n_hyp, key0, key1, xy,
-                                                th, hyp_counts, s_key);
+    // Trials read the points from LDS where they fit, else from global memory.
+    unsigned long long best;
+    if (paper_cluster(sp) && sp.n <= kPaperBlock)
+        best = paper_score(theta, sp, k, threadIdx.x, n_hyp, key0, key1, s_xy, th, hyp_counts,
+                           s_key);
+    else
+        best = paper_score(theta, sp, k, threadIdx.x, n_hyp, key0, key1,
+                           paper_cluster(sp) ? xy + sp.lo : xy, th, hyp_counts, s_key);
     paper_refit(theta, vd, sp, k, key0, key1, xy, th, best, o, s_sum, s_cnt);
 }
 

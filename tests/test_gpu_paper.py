@@ -198,3 +198,22 @@ def test_one_launch_path_matches_three_kernels(rv, oracle_mod, H):
             assert b["status"][6] == rv.RV_CLUSTER_TOO_LARGE
             skip = (6,)
         _compare(b, o, off, H, skip=skip)
+
+
+def test_preallocated_outputs_match_fresh_ones(rv):
+    f = synth.table_frame(16, 150)
+    t = torch.from_numpy(f.theta).cuda()
+    v = torch.from_numpy(f.vd).cuda()
+    o = torch.from_numpy(f.offsets).cuda()
+    for bits in (False, True):
+        out = rv.allocate_paper_outputs(f.n_clusters, f.n_points, 256, t.device, want_bits=bits,
+                                        debug=True)
+        for seed in (5, 6):
+            print(f"[gpu] rv_estimate_velocity_paper preallocated bits={bits} seed={seed}", flush=True)
+            a = rv.rv_estimate_velocity_paper(t, v, o, 256, seed, out=out)
+            b = rv.rv_estimate_velocity_paper(t, v, o, 256, seed, want_bits=bits, debug=True)
+            torch.cuda.synchronize()
+            assert set(a) == set(b)
+            for key in a:
+                x, y = a[key].cpu().numpy(), b[key].cpu().numpy()
+                assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), (bits, seed, key)
