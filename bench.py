@@ -94,6 +94,26 @@ def oracle_error_summary(vx, vy, heading, best, o_vx, o_vy, o_hd, o_best):
             "dv_bound": "2^-24 max(|vx_o|, |vy_o|) + 1e-12 m/s per cluster"}
 
 
+def warm_up(step, count: int, min_ms: float) -> int:
+    """Untimed warm-up: `count` steps, then more until at least min_ms of wall
+    time has passed since the first (the GPU's clocks rise over the first tens
+    of milliseconds of sustained work: after 10 dense frames the score kernel
+    still takes about 10 % longer than after 200).  Synchronises every few
+    steps so that the host clock follows the GPU.  step(i) runs warm-up step i;
+    returns the number of steps run."""
+    import torch
+
+    t0 = time.perf_counter()
+    n = 0
+    while n < count or (time.perf_counter() - t0) * 1e3 < min_ms:
+        step(n)
+        n += 1
+        if n % 8 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return n
+
+
 def profiled_traffic(workload: str, kernel: str = "score_kernel"):
     """HBM bytes per scoring launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a copy of known size), or None
@@ -213,9 +233,7 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
         graph.launch(stream)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    warm_steps = warm_up(lambda i: step(), args.warmup, args.min_warmup_ms)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     print(f"[bench] timing {args.steps} graph steps", file=sys.stderr, flush=True)
@@ -291,6 +309,8 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_steps_run": warm_steps,
+        "min_warmup_ms": args.min_warmup_ms,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -458,10 +478,9 @@ def paper_sweep_bench(args, torch, binding, synth, dev) -> int:
         # estimates frame after frame would hold them.
         out = binding.allocate_paper_outputs(f.n_clusters, f.n_points, H, dev)
         out_bits = binding.allocate_paper_outputs(f.n_clusters, f.n_points, H, dev, want_bits=True)
-        for i in range(args.warmup):
-            binding.rv_estimate_velocity_paper(t, v, o, H, synth.ransac_seed("paper", i), out=out,
-                                               stream=stream)
-        torch.cuda.synchronize()
+        warm_up(lambda i: binding.rv_estimate_velocity_paper(
+            t, v, o, H, synth.ransac_seed("paper", i), out=out, stream=stream),
+            args.warmup, args.min_warmup_ms)
         # Whole calls first, then the same number of calls with the library's
         # per-kernel events (each event is a queue marker that lengthens a call)
         # on the three-kernel path, whose stages are separate launches.
@@ -511,6 +530,7 @@ def paper_sweep_bench(args, torch, binding, synth, dev) -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "min_warmup_ms": args.min_warmup_ms,
         "ms_per_step": big["gpu_ms_per_frame"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -564,9 +584,7 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
                                                out=o, stream=stream)
 
         print(f"[bench] {form} form: warmup {args.warmup}, {args.steps} steps", file=sys.stderr, flush=True)
-        for _ in range(args.warmup):
-            call()
-        torch.cuda.synchronize()
+        warm_up(lambda i: call(), args.warmup, args.min_warmup_ms)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         binding.rv_stage_times()
@@ -630,6 +648,7 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "min_warmup_ms": args.min_warmup_ms,
         "ms_per_step": f16["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -690,6 +709,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--min-warmup-ms", type=float, default=100.0,
+                    help="after the warm-up steps, more untimed steps until this much time has passed")
     ap.add_argument("--workload", default="dense", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--latency-frames", type=int, default=1000,
                     help="frames timed from pinned host memory to results in host memory")
@@ -757,39 +778,49 @@ def main() -> int:
     offsets = torch.from_numpy(frame.offsets).to(dev)
     out = binding.allocate_outputs(K, N, n_hyp, dev, want_near=True)
     stream = torch.cuda.current_stream(dev)
+    # Arguments checked and marshalled once; each step passes a fresh seed.
+    estimate = binding.PreparedEstimate(theta, vd, offsets, n_hyp, tau, out, stream)
 
     def step(i):
-        binding.rv_estimate_velocity(theta, vd, offsets, n_hyp, tau, synth.ransac_seed(name, i),
-                                     out=out, stream=stream)
+        estimate(synth.ransac_seed(name, i))
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
+    warm_steps = warm_up(step, args.warmup, args.min_warmup_ms)
 
-    # Timed region: K steps between events on the launch stream.  The library's
-    # own events around each kernel (per-kernel durations) are recorded on every
-    # stage_sample_every-th step of the same region: each event is a marker in
-    # the stream's queue, and recorded on every step they would lengthen it.
+    # Timed region: K steps between two events on the launch stream.  The
+    # library's own events around each kernel (per-kernel durations) are
+    # recorded on every stage_sample_every-th step of the same region: each
+    # event is a marker in the stream's queue, and recorded on every step they
+    # would lengthen it.
     binding.rv_stage_times()  # drop anything recorded before
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev_start = torch.cuda.Event(enable_timing=True)
+    ev_end = torch.cuda.Event(enable_timing=True)
     every = max(1, args.stage_sample_every)
     torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    evs[0].record(stream)
+    ev_start.record(stream)
     for i in range(args.steps):
         sampled = i % every == 0
         if sampled:
             binding.rv_stage_timing(True)
-        step(args.warmup + i)
+        step(warm_steps + i)
         if sampled:
             binding.rv_stage_timing(False)
-        evs[i + 1].record(stream)
+    ev_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms, n_calls = binding.rv_stage_times()
-    ms_per_step = evs[0].elapsed_time(evs[-1]) / args.steps
+    ms_per_step = ev_start.elapsed_time(ev_end) / args.steps
+    # Spread of single steps: a second pass of K steps with an event between
+    # consecutive steps (outside the timed region; those markers lengthen
+    # short steps).
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for i in range(args.steps):
+        step(warm_steps + args.steps + i)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
     step_times = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     sec = ms_per_step / 1e3
     evals_per_s = evals / sec
@@ -883,6 +914,8 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warmup_steps_run": warm_steps,
+        "min_warmup_ms": args.min_warmup_ms,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -897,7 +930,8 @@ def main() -> int:
                         "distinct_frames": len(frames),
                         "scope": "pinned host frame -> H2D -> estimate -> D2H of per-cluster results"}
                        if lat else None),
-        "step_ms": {"median": percentile(step_times, 50), "p99": percentile(step_times, 99)},
+        "step_ms": {"median": percentile(step_times, 50), "p99": percentile(step_times, 99),
+                    "scope": "single steps, a second pass with an event between steps"},
         "stage_ms": dict(zip(binding.STAGE_NAMES, stage_avg)),
         "wall_ms_per_step": wall * 1e3 / args.steps,
         "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved_tflops,

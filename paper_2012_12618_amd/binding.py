@@ -278,6 +278,50 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     return {k: v for k, v in out.items() if k != "workspace"}
 
 
+class PreparedEstimate:
+    """rv_estimate_velocity with its tensors checked and their device pointers
+    taken once: each call passes only the seed, for callers that estimate frame
+    after frame in the same buffers (the tensors' contents may change between
+    calls, not their storage).  Holds references to every tensor it uses."""
+
+    def __init__(self, theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor, n_hyp: int,
+                 tau: float, out: dict, stream: torch.cuda.Stream | None = None):
+        self._lib = load_library()
+        device = theta.device
+        if device.type != "cuda":
+            raise ValueError("theta must be a GPU tensor")
+        n_points = int(theta.numel())
+        n_clusters = int(offsets.numel()) - 1
+        if n_clusters < 0 or int(vd.numel()) != n_points:
+            raise ValueError("offsets needs n_clusters + 1 entries; theta and vd must match")
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        ws = out["workspace"]
+        self._keep = (theta, vd, offsets, dict(out), stream)
+        self._head = (
+            _dev_ptr(theta, torch.float32, device, "theta"),
+            _dev_ptr(vd, torch.float32, device, "vd"),
+            _dev_ptr(offsets, torch.int32, device, "offsets"),
+            n_clusters, n_points, int(n_hyp), float(tau))
+        self._tail = (
+            _dev_ptr(out["vx"], torch.float32, device, "vx"),
+            _dev_ptr(out["vy"], torch.float32, device, "vy"),
+            _dev_ptr(out["heading"], torch.float32, device, "heading"),
+            _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
+            _dev_ptr(out["status"], torch.uint8, device, "status"),
+            _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau"),
+            _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
+            _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
+            _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+            ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream))
+        self.out = {k: v for k, v in out.items() if k != "workspace"}
+
+    def __call__(self, seed: int) -> dict:
+        _check(self._lib.rv_estimate_velocity(*self._head, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                              *self._tail))
+        return self.out
+
+
 def rv_stage_timing(enable: bool) -> None:
     _check(load_library().rv_stage_timing(1 if enable else 0))
 

@@ -294,3 +294,22 @@ def test_small_frame_path_matches_three_kernel_path(rv, oracle_mod):
         if name != "bad-offsets":
             o = oracle_mod.estimate_velocity(th, vd, off, H, tau, seed, debug=True)
             parity.report(f"{name}-fused", parity.check(th, vd, off, H, tau, seed, fused, o))
+
+
+def test_prepared_call_matches_the_plain_call(rv):
+    f, n_hyp, tau = synth.make_workload("small")
+    t = torch.from_numpy(f.theta).cuda()
+    v = torch.from_numpy(f.vd).cuda()
+    o = torch.from_numpy(f.offsets).cuda()
+    out = rv.allocate_outputs(f.n_clusters, f.n_points, n_hyp, t.device, want_near=True,
+                              debug=True)
+    prepared = rv.PreparedEstimate(t, v, o, n_hyp, tau, out)
+    for seed in (11, 12):
+        print(f"[gpu] rv_estimate_velocity prepared seed={seed}", flush=True)
+        a = {k: x.clone() for k, x in prepared(seed).items()}
+        b = rv.rv_estimate_velocity(t, v, o, n_hyp, tau, seed, want_near=True, debug=True)
+        torch.cuda.synchronize()
+        assert set(a) == set(b)
+        for key in a:
+            x, y = a[key].cpu().numpy(), b[key].cpu().numpy()
+            assert np.array_equal(x.view(np.uint8), y.view(np.uint8)), (seed, key)
