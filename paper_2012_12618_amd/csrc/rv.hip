@@ -164,6 +164,14 @@ __device__ __forceinline__ int size_class(int64_t n) {
 // Dispatch order of the clusters: a counting sort by decreasing size class, so
 // the longest workgroups start first (longest-processing-time-first).  The
 // order inside a class depends on atomics; it only affects scheduling.
+// Each thread takes clusters tid, tid + 256, ... in groups of kPlanUnroll, whose
+// offsets are all loaded before any of their LDS atomics; the exclusive scan
+// over the classes (largest first) is one wave's prefix sum, two classes per
+// lane.  This workgroup runs beside the staging workgroups and sets the prep
+// kernel's length when it is the slower one.
+constexpr int kPlanUnroll = 8;
+static_assert(kSizeClasses == 2 * kWave, "the class scan takes two classes per lane");
+
 __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
                            int64_t n_points, int32_t *__restrict__ order,
                            int64_t *__restrict__ n_big) {
@@ -171,21 +179,52 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
     __shared__ uint32_t start[kSizeClasses];
     for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) count[c] = 0;
     __syncthreads();
-    for (int64_t k = threadIdx.x; k < n_clusters; k += kPrepBlock)
-        atomicAdd(&count[size_class(cluster_span(off, k, n_points).n)], 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t at = 0;
-        for (int c = kSizeClasses - 1; c >= 0; --c) {
-            start[c] = at;
-            at += count[c];
-            if (c == kRefitBigClass) *n_big = at;  // clusters refit by a whole workgroup
+    const int64_t group = (int64_t)kPlanUnroll * kPrepBlock;
+    for (int64_t k0 = threadIdx.x; k0 < n_clusters; k0 += group) {
+        int cls[kPlanUnroll];
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u) {
+            const int64_t k = k0 + (int64_t)u * kPrepBlock;
+            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
         }
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u)
+            if (cls[u] >= 0) atomicAdd(&count[cls[u]], 1u);
     }
     __syncthreads();
-    for (int64_t k = threadIdx.x; k < n_clusters; k += kPrepBlock) {
-        const uint32_t pos = atomicAdd(&start[size_class(cluster_span(off, k, n_points).n)], 1u);
-        order[pos] = (int32_t)k;
+    if (threadIdx.x < kWave) {
+        // Position q = 0, 1, ... in the dispatch order is class kSizeClasses - 1 - q.
+        const int lane = threadIdx.x;
+        const int c_hi = kSizeClasses - 1 - 2 * lane, c_lo = c_hi - 1;
+        const uint32_t a = count[c_hi], b = count[c_lo];
+        uint32_t incl = a + b;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += y;
+        }
+        const uint32_t excl = incl - (a + b);
+        start[c_hi] = excl;
+        start[c_lo] = excl + a;
+        // Clusters refit by a whole workgroup: classes kRefitBigClass and up.
+        if (c_hi == kRefitBigClass) *n_big = excl + a;
+        if (c_lo == kRefitBigClass) *n_big = excl + a + b;
+    }
+    __syncthreads();
+    for (int64_t k0 = threadIdx.x; k0 < n_clusters; k0 += group) {
+        int cls[kPlanUnroll];
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u) {
+            const int64_t k = k0 + (int64_t)u * kPrepBlock;
+            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u) {
+            if (cls[u] >= 0) {
+                const uint32_t pos = atomicAdd(&start[cls[u]], 1u);
+                order[pos] = (int32_t)(k0 + (int64_t)u * kPrepBlock);
+            }
+        }
     }
 }
 
