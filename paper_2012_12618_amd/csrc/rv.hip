@@ -172,6 +172,17 @@ __device__ __forceinline__ int size_class(int64_t n) {
 constexpr int kPlanUnroll = 8;
 static_assert(kSizeClasses == 2 * kWave, "the class scan takes two classes per lane");
 
+// Exclusive prefix sum of x over the lanes of one full wave.
+__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t x, int lane) {
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += y;
+    }
+    return incl - x;
+}
+
 __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
                            int64_t n_points, int32_t *__restrict__ order,
                            int64_t *__restrict__ n_big) {
@@ -197,13 +208,7 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
         const int lane = threadIdx.x;
         const int c_hi = kSizeClasses - 1 - 2 * lane, c_lo = c_hi - 1;
         const uint32_t a = count[c_hi], b = count[c_lo];
-        uint32_t incl = a + b;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += y;
-        }
-        const uint32_t excl = incl - (a + b);
+        const uint32_t excl = wave_exclusive_sum(a + b, lane);
         start[c_hi] = excl;
         start[c_lo] = excl + a;
         // Clusters refit by a whole workgroup: classes kRefitBigClass and up.
@@ -1162,16 +1167,19 @@ __global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(
 }
 
 // Start of each size class in the dispatch order (largest class first).
-__global__ __launch_bounds__(64) void batch_scan_kernel(uint32_t *__restrict__ hist,
-                                                        int64_t *__restrict__ n_big) {
-    if (threadIdx.x != 0) return;
-    uint32_t at = 0;
-    for (int c = kSizeClasses - 1; c >= 0; --c) {
-        const uint32_t n = hist[c];
-        hist[c] = at;
-        at += n;
-        if (c == kRefitBigClass) *n_big = at;  // clusters refit by a whole workgroup
-    }
+__global__ __launch_bounds__(kWave) void batch_scan_kernel(uint32_t *__restrict__ hist,
+                                                           int64_t *__restrict__ n_big) {
+    // One wave, two classes per lane (position q in the dispatch order is class
+    // kSizeClasses - 1 - q); each lane reads and rewrites only its own two.
+    const int lane = threadIdx.x;
+    const int c_hi = kSizeClasses - 1 - 2 * lane, c_lo = c_hi - 1;
+    const uint32_t a = hist[c_hi], b = hist[c_lo];
+    const uint32_t excl = wave_exclusive_sum(a + b, lane);
+    hist[c_hi] = excl;
+    hist[c_lo] = excl + a;
+    // Clusters refit by a whole workgroup: classes kRefitBigClass and up.
+    if (c_hi == kRefitBigClass) *n_big = excl + a;
+    if (c_lo == kRefitBigClass) *n_big = excl + a + b;
 }
 
 // Places every cluster in the dispatch order (one global atomic per class and
