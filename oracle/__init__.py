@@ -77,6 +77,8 @@ def _load():
     lib.oracle_fit_hypothesis.restype = ctypes.c_int
     lib.oracle_fit_hypothesis.argtypes = [P, P, P, i64, i64, f32, u64, i64, i64, f64,
                                           P, P, P, P, P, P, P, P]
+    lib.oracle_refit_mask.restype = ctypes.c_int
+    lib.oracle_refit_mask.argtypes = [P, P, P, i64, P, P, P, P, P]
     lib.oracle_all_pairs_best.restype = i32
     lib.oracle_all_pairs_best.argtypes = [P, P, i32, f32, P, P]
     lib.oracle_estimate_velocity_paper.restype = ctypes.c_int
@@ -231,6 +233,35 @@ def fit_hypothesis(theta, vd, offsets, tau: float, seed: int, k: int, h: int, *,
         raise ValueError("oracle rejected its arguments")
     return HypothesisFit(vx.value, vy.value, hd.value, n_in.value, n_near.value, st.value,
                          mask[:n], near[:n])
+
+
+@dataclass
+class MaskFit:
+    vx: float
+    vy: float
+    heading: float
+    n_inliers: int
+    status: int
+
+
+def refit_on_mask(theta, vd, mask) -> MaskFit:
+    """Least-squares refit and heading of ONE cluster (its theta, vd) on a given
+    inlier set ``mask`` (bool or uint8 per point; non-finite points skipped),
+    Sec. 3.2 Eq. 7 and Eq. 8, summed in point order like the oracle's own refit."""
+    lib = _load()
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    v = np.ascontiguousarray(vd, dtype=np.float32)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    n = th.shape[0]
+    if v.shape[0] != n or m.shape[0] != n:
+        raise ValueError("theta, vd and mask differ in length")
+    vx, vy, hd = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n_in, st = ctypes.c_int32(), ctypes.c_uint8()
+    rc = lib.oracle_refit_mask(_ptr(th), _ptr(v), _ptr(m), n, ctypes.byref(vx), ctypes.byref(vy),
+                               ctypes.byref(hd), ctypes.byref(n_in), ctypes.byref(st))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return MaskFit(vx.value, vy.value, hd.value, n_in.value, st.value)
 
 
 def all_pairs_best(theta, vd, tau: float):

@@ -179,6 +179,38 @@ struct fit {
     uint8_t status;
 };
 
+/* Normal-equation sums of the least-squares refit (Sec. 3.2, Eq. 7):
+   A^T A = [[scc, scs], [scs, sss]] and A^T v_d = (scv, ssv). */
+struct sums {
+    double scc, scs, sss, scv, ssv;
+};
+
+static void add_point(struct sums *S, double c, double s, double v)
+{
+    S->scc += c * c;
+    S->scs += c * s;
+    S->sss += s * s;
+    S->scv += c * v;
+    S->ssv += s * v;
+}
+
+/* Solves the 2x2 normal equations and takes the heading (Eq. 8, atan2). */
+static void solve_sums(const struct sums *S, int64_t n_in, struct fit *f)
+{
+    double det = S->scc * S->sss - S->scs * S->scs;
+    if (n_in < 2 || !(det > 0.0)) {
+        f->vx = NAN;
+        f->vy = NAN;
+        f->heading = NAN;
+        f->status = OR_CLUSTER_SINGULAR_REFIT;
+        return;
+    }
+    f->vx = (S->sss * S->scv - S->scs * S->ssv) / det;
+    f->vy = (S->scc * S->ssv - S->scs * S->scv) / det;
+    f->heading = atan2(f->vy, f->vx);
+    f->status = OR_CLUSTER_OK;
+}
+
 /*
  * Least-squares refit on the inliers of hypothesis (hvx, hvy) (Sec. 3.2,
  * Eq. 7, Alg. 2): every finite point with |v_d - hvx cos - hvy sin| < tau
@@ -191,7 +223,7 @@ static void refit(const float *vd, const double *c, const double *s, const uint8
                   int64_t n, double hvx, double hvy, double tau, double near_window,
                   uint8_t *mask, uint8_t *near_mask, struct fit *f)
 {
-    double scc = 0.0, scs = 0.0, sss = 0.0, scv = 0.0, ssv = 0.0;
+    struct sums S = {0.0, 0.0, 0.0, 0.0, 0.0};
     int64_t n_in = 0, n_near = 0;
     for (int64_t p = 0; p < n; ++p) {
         if (mask) mask[p] = 0;
@@ -208,26 +240,11 @@ static void refit(const float *vd, const double *c, const double *s, const uint8
             continue;
         n_in += 1;
         if (mask) mask[p] = 1;
-        scc += c[p] * c[p];
-        scs += c[p] * s[p];
-        sss += s[p] * s[p];
-        scv += c[p] * v;
-        ssv += s[p] * v;
+        add_point(&S, c[p], s[p], v);
     }
     f->n_inliers = (int32_t)n_in;
     f->n_near = (int32_t)n_near;
-    double det = scc * sss - scs * scs;
-    if (n_in < 2 || !(det > 0.0)) {
-        f->vx = NAN;
-        f->vy = NAN;
-        f->heading = NAN;
-        f->status = OR_CLUSTER_SINGULAR_REFIT;
-        return;
-    }
-    f->vx = (sss * scv - scs * ssv) / det;
-    f->vy = (scc * ssv - scs * scv) / det;
-    f->heading = atan2(f->vy, f->vx);
-    f->status = OR_CLUSTER_OK;
+    solve_sums(&S, n_in, f);
 }
 
 static void estimate_cluster(struct job *J, int64_t r, double *c, double *s, uint8_t *ok)
@@ -569,4 +586,40 @@ int oracle_fit_hypothesis(const float *theta, const float *vd, const int32_t *of
     }
     free(c); free(s); free(ok);
     return rc;
+}
+
+/*
+ * Least-squares refit (Sec. 3.2, Eq. 7, Alg. 2) and heading (Eq. 8) of one
+ * cluster of n points on a GIVEN inlier set: point p is used when mask[p] is
+ * nonzero and its azimuth and Doppler value are finite.  The sums run in point
+ * order, as in the oracle's own refit, so on the oracle's own mask the result
+ * is the same bit for bit.  Used to check a refit whose inlier set differs from
+ * the oracle's classification at points within rounding of tau.  status is
+ * OR_CLUSTER_OK or OR_CLUSTER_SINGULAR_REFIT.  Returns 0, or -1 for invalid
+ * arguments.
+ */
+int oracle_refit_mask(const float *theta, const float *vd, const uint8_t *mask, int64_t n,
+                      double *vx, double *vy, double *heading, int32_t *n_inliers,
+                      uint8_t *status)
+{
+    if (n < 0 || (n > 0 && (!theta || !vd || !mask)) || !vx || !vy || !heading ||
+        !n_inliers || !status)
+        return -1;
+    struct sums S = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t n_in = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        if (!mask[p] || !isfinite(theta[p]) || !isfinite(vd[p]))
+            continue;
+        double t = (double)theta[p];
+        n_in += 1;
+        add_point(&S, cos(t), sin(t), (double)vd[p]);
+    }
+    struct fit f;
+    solve_sums(&S, n_in, &f);
+    *vx = f.vx;
+    *vy = f.vy;
+    *heading = f.heading;
+    *n_inliers = (int32_t)n_in;
+    *status = f.status;
+    return 0;
 }

@@ -91,13 +91,14 @@ def test_band_counts_and_near_window_hand_worked(oracle_mod):
 def test_zero_band_is_the_count(oracle_mod):
     # With zero width both band edges are the strict count itself, for every
     # hypothesis of the small workload (and 0 for the invalid ones).
-    frame, seed, tau = synth.make_workload("small")
-    r = oracle_mod.estimate_velocity(frame.theta, frame.vd, frame.offsets, 256, tau, seed,
+    frame, H, tau = synth.make_workload("small")
+    seed = synth.ransac_seed("small")
+    r = oracle_mod.estimate_velocity(frame.theta, frame.vd, frame.offsets, H, tau, seed,
                                      debug=True, band_abs=0.0, band_rel=0.0)
     assert np.array_equal(r.hyp_count_lo, r.hyp_count)
     assert np.array_equal(r.hyp_count_hi, r.hyp_count)
     # and the default band brackets it
-    d = oracle_mod.estimate_velocity(frame.theta, frame.vd, frame.offsets, 256, tau, seed,
+    d = oracle_mod.estimate_velocity(frame.theta, frame.vd, frame.offsets, H, tau, seed,
                                      debug=True)
     assert np.array_equal(d.hyp_count, r.hyp_count)
     assert np.all(d.hyp_count_lo <= d.hyp_count) and np.all(d.hyp_count <= d.hyp_count_hi)

@@ -7,7 +7,8 @@ paper number; every pin is something the mathematics fixes:
   * noise-free clusters: each hypothesis and the refit recover the truth within
     the error bound that float32 rounding of v_d implies (Cramer / least squares);
   * the refit equals numpy.linalg.lstsq and pinv (the paper's comparator) on
-    the same inlier set;
+    the same inlier set, and the refit on a given inlier set equals the
+    oracle's own refit on its mask (bitwise) and lstsq on other masks;
   * noise-free clusters with outliers: the inlier set is exactly the true one;
   * small clusters: RANSAC's best count equals an exhaustive all-pairs search;
   * rotation, power-of-two scaling, sign flip, reflection, batch independence;
@@ -113,6 +114,43 @@ def test_noiseless_hypotheses_and_refit_recover_truth(oracle_mod):
         bound = np.linalg.norm(np.linalg.pinv(A), 2) * np.linalg.norm(dv) * 1.01 + 1e-12
         assert math.hypot(r.vx[k] - vx, r.vy[k] - vy) <= bound
         assert abs(math.remainder(r.heading[k] - math.atan2(vy, vx), 2 * math.pi)) < 1e-5
+
+
+def test_refit_on_a_given_mask(oracle_mod):
+    # The refit on a caller's inlier set (used when a GPU mask differs from the
+    # oracle's at points within rounding of tau): on the oracle's own mask it is
+    # the oracle's refit bit for bit (same sums in the same order); on other
+    # masks it equals numpy.linalg.lstsq; non-finite points are skipped; fewer
+    # than two points or one azimuth only is singular.
+    frame, H, tau = synth.make_workload("small")
+    r = oracle_mod.estimate_velocity(frame.theta, frame.vd, frame.offsets, H, tau, seed=21)
+    rng = np.random.default_rng(5)
+    for k in range(frame.n_clusters):
+        lo, hi = frame.offsets[k], frame.offsets[k + 1]
+        th, vd = frame.theta[lo:hi], frame.vd[lo:hi]
+        own = oracle_mod.refit_on_mask(th, vd, r.inlier_mask[lo:hi])
+        assert own.n_inliers == r.n_inliers[k] and own.status == r.status[k]
+        assert (own.vx, own.vy, own.heading) == (r.vx[k], r.vy[k], r.heading[k])
+        m = rng.random(hi - lo) < 0.6
+        m[:2] = True
+        f = oracle_mod.refit_on_mask(th, vd, m)
+        t = th.astype(np.float64)[m]
+        A = np.stack([np.cos(t), np.sin(t)], axis=1)
+        x = np.linalg.lstsq(A, vd.astype(np.float64)[m], rcond=None)[0]
+        assert f.n_inliers == m.sum() and f.status == oracle_mod.CLUSTER_OK
+        assert abs(f.vx - x[0]) <= 1e-10 * (1 + abs(x[0]))
+        assert abs(f.vy - x[1]) <= 1e-10 * (1 + abs(x[1]))
+        assert abs(math.remainder(f.heading - math.atan2(x[1], x[0]), 2 * math.pi)) <= 1e-10
+    th = np.array([0.1, 0.4, 0.7, np.nan, 0.3], np.float32)
+    vd = np.array([1.0, 2.0, 3.0, 4.0, np.inf], np.float32)
+    f = oracle_mod.refit_on_mask(th, vd, np.ones(5, bool))
+    g = oracle_mod.refit_on_mask(th[:3], vd[:3], np.ones(3, bool))
+    assert f.n_inliers == 3 and (f.vx, f.vy) == (g.vx, g.vy)
+    assert oracle_mod.refit_on_mask(th, vd, np.array([1, 0, 0, 0, 0])).status == \
+        oracle_mod.CLUSTER_SINGULAR_REFIT
+    same = np.full(4, 0.25, np.float32)
+    assert oracle_mod.refit_on_mask(same, vd[:4], np.ones(4, bool)).status == \
+        oracle_mod.CLUSTER_SINGULAR_REFIT
 
 
 def test_heading_quadrants(oracle_mod):
