@@ -266,11 +266,14 @@ typedef struct {
     int32_t max_batch_frames;    /* frames per launch, >= 1 */
     int32_t n_streams;           /* launch slots in flight, [1, 8] */
     int32_t max_waiting_frames;  /* submitted, not yet launched frames before RV_ERR_BUSY, >= 1 */
+    int32_t keep_inlier_bits;    /* nonzero: every frame's inlier mask (Sec. 3.1: the OR of its
+                                    clusters' masks) is computed and kept for rv_server_result;
+                                    it costs ceil(n_points / 32) words per frame in the arena */
     rv_tuning_t tuning;
 } rv_server_config_t;
 
 /* Defaults: n_hyp 512, tau 0.15, 16 GiB, 64 frames per launch, 2 slots,
-   1024 waiting frames, default tuning. */
+   1024 waiting frames, no inlier masks, default tuning. */
 void rv_server_config_default(rv_server_config_t *cfg);
 
 /* Device memory that one frame of n_clusters clusters and n_points points
@@ -308,12 +311,16 @@ typedef struct {
 } rv_frame_times_t;
 
 /* Copies a ready ticket's per-cluster results into HOST arrays of its
-   n_clusters entries (n_near_tau and times nullable) and forgets the ticket.
-   RV_OK, RV_ERR_INVALID_ARG (unknown ticket, NULL output) or RV_ERR_BUSY (not
-   ready yet). */
+   n_clusters entries and forgets the ticket.  Nullable: n_near_tau, best_hyp
+   (index of each cluster's kept hypothesis, -1 if none, as rv_estimate_velocity
+   reports it), inlier_bits (HOST array of ceil(n_points / 32) words: bit p % 32
+   of word p / 32 is the frame's point p; only from a server created with
+   keep_inlier_bits) and times.  RV_OK, RV_ERR_INVALID_ARG (unknown ticket, NULL
+   required output, inlier_bits from a server that keeps no masks; the ticket is
+   then kept) or RV_ERR_BUSY (not ready yet). */
 int rv_server_result(rv_server_t *server, uint64_t ticket, float *vx, float *vy, float *heading,
-                     int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
-                     rv_frame_times_t *times);
+                     int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau, int32_t *best_hyp,
+                     uint32_t *inlier_bits, rv_frame_times_t *times);
 
 typedef struct {
     int64_t frames_submitted, frames_done, batches, busy_rejections;

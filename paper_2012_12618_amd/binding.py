@@ -69,7 +69,7 @@ class RVServerConfig(ctypes.Structure):
     _fields_ = [("n_hyp", ctypes.c_int32), ("tau", ctypes.c_float),
                 ("hbm_budget_bytes", ctypes.c_size_t), ("max_batch_frames", ctypes.c_int32),
                 ("n_streams", ctypes.c_int32), ("max_waiting_frames", ctypes.c_int32),
-                ("tuning", RVTuning)]
+                ("keep_inlier_bits", ctypes.c_int32), ("tuning", RVTuning)]
 
 
 class RVFrameTimes(ctypes.Structure):
@@ -154,7 +154,7 @@ def load_library() -> ctypes.CDLL:
     lib.rv_server_wait.restype = ctypes.c_int
     lib.rv_server_wait.argtypes = [P, ctypes.c_uint64, i64]
     lib.rv_server_result.restype = ctypes.c_int
-    lib.rv_server_result.argtypes = [P, ctypes.c_uint64, P, P, P, P, P, P, P]
+    lib.rv_server_result.argtypes = [P, ctypes.c_uint64, P, P, P, P, P, P, P, P, P]
     lib.rv_server_stats.restype = ctypes.c_int
     lib.rv_server_stats.argtypes = [P, P]
     lib.rv_server_destroy.restype = None
@@ -176,7 +176,10 @@ def rv_workspace_bytes(n_clusters: int, n_points: int, n_hyp: int) -> int:
     return int(load_library().rv_workspace_bytes(int(n_clusters), int(n_points), int(n_hyp)))
 
 
-def _dev_ptr(t: torch.Tensor | None, dtype: torch.dtype, device: torch.device, name: str):
+def _dev_ptr(t: torch.Tensor | None, dtype: torch.dtype, device: torch.device, name: str,
+             numel: int | None = None):
+    """Device pointer of a checked tensor; ``numel``: the elements the kernels
+    write or read through it (a smaller tensor raises before anything runs)."""
     if t is None:
         return None
     if t.dtype != dtype:
@@ -185,7 +188,27 @@ def _dev_ptr(t: torch.Tensor | None, dtype: torch.dtype, device: torch.device, n
         raise ValueError(f"{name} must be on {device}, got {t.device}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, {numel} needed")
     return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
+
+
+def _output_ptrs(out: dict, device, n_clusters: int, n_points: int, n_hyp: int) -> tuple:
+    """The output pointers of the estimate entry points, in their C order
+    (vx, vy, heading, n_inliers, status, n_near_tau, inlier_bits, hyp_counts,
+    best_hyp), each checked for dtype, device, layout and size."""
+    K = n_clusters
+    return (
+        _dev_ptr(out["vx"], torch.float32, device, "vx", K),
+        _dev_ptr(out["vy"], torch.float32, device, "vy", K),
+        _dev_ptr(out["heading"], torch.float32, device, "heading", K),
+        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers", K),
+        _dev_ptr(out["status"], torch.uint8, device, "status", K),
+        _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau", K),
+        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits", (n_points + 31) // 32),
+        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts", K * int(n_hyp)),
+        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp", K),
+    )
 
 
 def allocate_outputs(n_clusters: int, n_points: int, n_hyp: int, device, *,
@@ -261,15 +284,7 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
         _dev_ptr(vd, torch.float32, device, "vd"),
         _dev_ptr(offsets, torch.int32, device, "offsets"),
         n_clusters, n_points, int(n_hyp), float(tau), int(seed) & 0xFFFFFFFFFFFFFFFF,
-        _dev_ptr(out["vx"], torch.float32, device, "vx"),
-        _dev_ptr(out["vy"], torch.float32, device, "vy"),
-        _dev_ptr(out["heading"], torch.float32, device, "heading"),
-        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
-        _dev_ptr(out["status"], torch.uint8, device, "status"),
-        _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau"),
-        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
-        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
-        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+        *_output_ptrs(out, device, n_clusters, n_points, n_hyp),
         ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream),
     )
     _check(code)
@@ -304,15 +319,7 @@ class PreparedEstimate:
             _dev_ptr(offsets, torch.int32, device, "offsets"),
             n_clusters, n_points, int(n_hyp), float(tau))
         self._tail = (
-            _dev_ptr(out["vx"], torch.float32, device, "vx"),
-            _dev_ptr(out["vy"], torch.float32, device, "vy"),
-            _dev_ptr(out["heading"], torch.float32, device, "heading"),
-            _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
-            _dev_ptr(out["status"], torch.uint8, device, "status"),
-            _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau"),
-            _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
-            _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
-            _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+            *_output_ptrs(out, device, n_clusters, n_points, n_hyp),
             ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream))
         self.out = {k: v for k, v in out.items() if k != "workspace"}
 
@@ -398,15 +405,7 @@ def _batch_args(theta, vd, offsets, frame_offsets, seeds, n_hyp, tau, out, tunin
         _dev_ptr(frame_offsets, torch.int32, device, "frame_offsets"),
         _dev_ptr(seeds, torch.int64, device, "seeds"),
         n_frames, n_clusters, n_points, int(n_hyp), float(tau),
-        _dev_ptr(out["vx"], torch.float32, device, "vx"),
-        _dev_ptr(out["vy"], torch.float32, device, "vy"),
-        _dev_ptr(out["heading"], torch.float32, device, "heading"),
-        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
-        _dev_ptr(out["status"], torch.uint8, device, "status"),
-        _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau"),
-        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
-        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
-        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+        *_output_ptrs(out, device, n_clusters, n_points, n_hyp),
         ctypes.byref(tune),
         ctypes.c_void_p(ws.data_ptr()), int(ws.numel()),
     ]
@@ -527,14 +526,15 @@ def rv_estimate_velocity_paper(theta: torch.Tensor, vd: torch.Tensor, offsets: t
         _dev_ptr(theta, torch.float32, device, "theta"), _dev_ptr(vd, torch.float32, device, "vd"),
         _dev_ptr(offsets, torch.int32, device, "offsets"), n_clusters, n_points, int(n_hyp),
         int(seed) & 0xFFFFFFFFFFFFFFFF,
-        _dev_ptr(out["vx"], torch.float32, device, "vx"), _dev_ptr(out["vy"], torch.float32, device, "vy"),
-        _dev_ptr(out["heading"], torch.float32, device, "heading"),
-        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers"),
-        _dev_ptr(out["status"], torch.uint8, device, "status"),
-        _dev_ptr(out["thresh"], torch.float64, device, "thresh"),
-        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits"),
-        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts"),
-        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp"),
+        _dev_ptr(out["vx"], torch.float32, device, "vx", n_clusters),
+        _dev_ptr(out["vy"], torch.float32, device, "vy", n_clusters),
+        _dev_ptr(out["heading"], torch.float32, device, "heading", n_clusters),
+        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers", n_clusters),
+        _dev_ptr(out["status"], torch.uint8, device, "status", n_clusters),
+        _dev_ptr(out["thresh"], torch.float64, device, "thresh", n_clusters),
+        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits", (n_points + 31) // 32),
+        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts", n_clusters * int(n_hyp)),
+        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp", n_clusters),
         ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream)))
     if owned:
         _used_on(stream, list(out.values()) + [ws])
@@ -571,7 +571,7 @@ class RVServer:
         handle = ctypes.c_void_p()
         _check(lib.rv_server_create(ctypes.byref(self.cfg), ctypes.byref(handle)))
         self._h = handle
-        self._sizes: dict[int, int] = {}
+        self._sizes: dict[int, tuple[int, int]] = {}
 
     def submit(self, theta: np.ndarray, vd: np.ndarray, offsets: np.ndarray, seed: int) -> int:
         """Queue one frame; returns its ticket.  Raises RVError (code RV_ERR_BUSY when full)."""
@@ -586,7 +586,7 @@ class RVServer:
             self._h, theta.ctypes.data_as(ctypes.c_void_p), vd.ctypes.data_as(ctypes.c_void_p),
             offsets.ctypes.data_as(ctypes.c_void_p), n_clusters, n_points,
             int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(t)))
-        self._sizes[int(t.value)] = n_clusters
+        self._sizes[int(t.value)] = (n_clusters, n_points)
         return int(t.value)
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
@@ -596,17 +596,25 @@ class RVServer:
         return rc == 1
 
     def result(self, ticket: int) -> dict:
-        """Per-cluster results of a finished ticket (waits for it first)."""
+        """Per-cluster results of a finished ticket (waits for it first); with a
+        server configured with keep_inlier_bits also the frame's inlier mask
+        (``inlier_bits``, int32 words)."""
         self.wait(ticket)
-        K = self._sizes.pop(int(ticket))
+        K, N = self._sizes[int(ticket)]
         out = {"vx": np.empty(K, np.float32), "vy": np.empty(K, np.float32),
                "heading": np.empty(K, np.float32), "n_inliers": np.empty(K, np.int32),
-               "status": np.empty(K, np.uint8), "n_near_tau": np.empty(K, np.int32)}
+               "status": np.empty(K, np.uint8), "n_near_tau": np.empty(K, np.int32),
+               "best_hyp": np.empty(K, np.int32)}
+        bits = np.zeros((N + 31) // 32, np.int32) if self.cfg.keep_inlier_bits else None
         times = RVFrameTimes()
         ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
         _check(load_library().rv_server_result(
             self._h, int(ticket), ptr(out["vx"]), ptr(out["vy"]), ptr(out["heading"]),
-            ptr(out["n_inliers"]), ptr(out["status"]), ptr(out["n_near_tau"]), ctypes.byref(times)))
+            ptr(out["n_inliers"]), ptr(out["status"]), ptr(out["n_near_tau"]),
+            ptr(out["best_hyp"]), None if bits is None else ptr(bits), ctypes.byref(times)))
+        del self._sizes[int(ticket)]
+        if bits is not None:
+            out["inlier_bits"] = bits
         out["times"] = {n: int(getattr(times, n)) for n, _ in RVFrameTimes._fields_}
         return out
 

@@ -142,11 +142,12 @@ struct BatchPlan {
     size_t offsets, frame_off, seeds, meta_bytes;
     size_t theta, vd, ws, ws_bytes;
     size_t out, out_bytes;                      // outputs block, and within it:
-    size_t o_vx, o_vy, o_heading, o_inl, o_near, o_status;
+    size_t o_vx, o_vy, o_heading, o_inl, o_near, o_best, o_bits, o_status;
+    size_t bits_words;                          // 0 unless the inlier mask is kept
     size_t total;
 };
 
-BatchPlan plan_batch(int64_t F, int64_t K, int64_t N, int32_t H) {
+BatchPlan plan_batch(int64_t F, int64_t K, int64_t N, int32_t H, bool bits) {
     BatchPlan p;
     size_t at = 0;
     p.offsets = at; at = align_up(at + (size_t)(K + 1) * 4);
@@ -165,6 +166,9 @@ BatchPlan plan_batch(int64_t F, int64_t K, int64_t N, int32_t H) {
     p.o_heading = o; o = align_up(o + (size_t)K * 4);
     p.o_inl = o; o = align_up(o + (size_t)K * 4);
     p.o_near = o; o = align_up(o + (size_t)K * 4);
+    p.o_best = o; o = align_up(o + (size_t)K * 4);
+    p.bits_words = bits ? ((size_t)N + 31) / 32 : 0;
+    p.o_bits = o; o = align_up(o + p.bits_words * 4);
     p.o_status = o; o = align_up(o + (size_t)K);
     p.out_bytes = o;
     p.total = at + o;
@@ -182,8 +186,9 @@ struct Frame {
     int state = kWaiting;
     rv_frame_times_t times{};
     std::vector<float> vx, vy, heading;
-    std::vector<int32_t> n_inliers, n_near;
+    std::vector<int32_t> n_inliers, n_near, best;
     std::vector<uint8_t> status;
+    std::vector<uint32_t> bits;  // its inlier mask, when the server keeps masks
 
     const float *theta() const { return (const float *)in; }
     const float *vd() const { return (const float *)in + N; }
@@ -239,9 +244,29 @@ int free_slot(const rv_server *s) {
     return -1;
 }
 
+BatchPlan plan_for(const rv_server *s, int64_t F, int64_t K, int64_t N) {
+    return plan_batch(F, K, N, s->cfg.n_hyp, s->cfg.keep_inlier_bits != 0);
+}
+
 bool head_fits(const rv_server *s) {
     const Frame *f = s->waiting.front();
-    return plan_batch(1, f->K, f->N, s->cfg.n_hyp).total <= s->arena.largest_free();
+    return plan_for(s, 1, f->K, f->N).total <= s->arena.largest_free();
+}
+
+// Bits [p0, p0 + n) of a batch's inlier mask (n_words words), re-based to start
+// at bit 0 of out[ceil(n / 32)]; bits of the next frame in the last word are
+// cleared.
+void extract_bits(const uint32_t *w, size_t n_words, int64_t p0, int64_t n, uint32_t *out) {
+    const int64_t nw = (n + 31) / 32;
+    const int sh = (int)(p0 & 31);
+    const size_t base = (size_t)(p0 >> 5);
+    for (int64_t i = 0; i < nw; ++i) {
+        const size_t a = base + (size_t)i;
+        const uint64_t lo = a < n_words ? w[a] : 0u;
+        const uint64_t hi = a + 1 < n_words ? w[a + 1] : 0u;
+        out[i] = (uint32_t)(((hi << 32) | lo) >> sh);
+    }
+    if ((n & 31) != 0) out[nw - 1] &= (1u << (n & 31)) - 1u;
 }
 
 bool ensure_pinned(PinnedPool &pool, void **p, size_t *cap, size_t need) {
@@ -293,8 +318,8 @@ int launch_slot(rv_server *s, Slot &sl) {
         (const int32_t *)(d + p.frame_off), (const uint64_t *)(d + p.seeds), F, sl.K, sl.N,
         s->cfg.n_hyp, s->cfg.tau, (float *)(o + p.o_vx), (float *)(o + p.o_vy),
         (float *)(o + p.o_heading), (int32_t *)(o + p.o_inl), (uint8_t *)(o + p.o_status),
-        (int32_t *)(o + p.o_near), nullptr, nullptr, nullptr, &s->cfg.tuning, d + p.ws,
-        p.ws_bytes, st);
+        (int32_t *)(o + p.o_near), p.bits_words > 0 ? (uint32_t *)(o + p.o_bits) : nullptr,
+        nullptr, (int32_t *)(o + p.o_best), &s->cfg.tuning, d + p.ws, p.ws_bytes, st);
     if (rc != RV_OK) return rc;
     if (sl.K > 0) {
         e = hipMemcpyAsync(sl.result, o, p.out_bytes, hipMemcpyDeviceToHost, st);
@@ -325,12 +350,12 @@ void scheduler_loop(rv_server *s) {
             if (F >= s->cfg.max_batch_frames) break;
             const int64_t K2 = K + f->K, N2 = N + f->N;
             if (K2 > INT32_MAX || N2 > INT32_MAX) break;
-            if (plan_batch(F + 1, K2, N2, s->cfg.n_hyp).total > room) break;
+            if (plan_for(s, F + 1, K2, N2).total > room) break;
             ++F;
             K = K2;
             N = N2;
         }
-        sl.plan = plan_batch(F, K, N, s->cfg.n_hyp);
+        sl.plan = plan_for(s, F, K, N);
         sl.arena_off = s->arena.alloc(sl.plan.total);  // fits: total <= room
         sl.K = K;
         sl.N = N;
@@ -388,6 +413,13 @@ void completer_loop(rv_server *s) {
                                  (const int32_t *)(r + p.o_near) + c0 + K);
                 f->status.assign((const uint8_t *)(r + p.o_status) + c0,
                                  (const uint8_t *)(r + p.o_status) + c0 + K);
+                f->best.assign((const int32_t *)(r + p.o_best) + c0,
+                               (const int32_t *)(r + p.o_best) + c0 + K);
+                if (p.bits_words > 0) {
+                    f->bits.resize(((size_t)f->N + 31) / 32);
+                    extract_bits((const uint32_t *)(r + p.o_bits), p.bits_words, f->p0, f->N,
+                                 f->bits.data());
+                }
             }
         }
         lk.lock();
@@ -468,7 +500,7 @@ size_t rv_server_frame_bytes(const rv_server_config_t *cfg, int64_t n_clusters, 
     if (cfg == nullptr || n_clusters < 0 || n_points < 0 || n_clusters > INT32_MAX ||
         n_points > INT32_MAX || cfg->n_hyp < 1)
         return 0;
-    return plan_batch(1, n_clusters, n_points, cfg->n_hyp).total;
+    return plan_batch(1, n_clusters, n_points, cfg->n_hyp, cfg->keep_inlier_bits != 0).total;
 }
 
 int rv_server_create(const rv_server_config_t *cfg, rv_server_t **server) {
@@ -537,7 +569,7 @@ int rv_server_submit(rv_server_t *s, const float *theta, const float *vd,
     for (int64_t k = 0; k < n_clusters; ++k)
         if (cluster_offsets[k + 1] < cluster_offsets[k])
             return fail(RV_ERR_INVALID_ARG, "cluster_offsets must be non-decreasing");
-    const size_t need = plan_batch(1, n_clusters, n_points, s->cfg.n_hyp).total;
+    const size_t need = plan_for(s, 1, n_clusters, n_points).total;
     if (need > s->cfg.hbm_budget_bytes)
         return fail(RV_ERR_INVALID_ARG, "frame needs %zu bytes of device memory, budget is %zu",
                     need, s->cfg.hbm_budget_bytes);
@@ -599,8 +631,8 @@ int rv_server_wait(rv_server_t *s, uint64_t ticket, int64_t timeout_ms) {
 }
 
 int rv_server_result(rv_server_t *s, uint64_t ticket, float *vx, float *vy, float *heading,
-                     int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
-                     rv_frame_times_t *times) {
+                     int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau, int32_t *best_hyp,
+                     uint32_t *inlier_bits, rv_frame_times_t *times) {
     g_error[0] = '\0';
     if (s == nullptr) return fail(RV_ERR_INVALID_ARG, "server is NULL");
     Frame *f = nullptr;
@@ -614,6 +646,8 @@ int rv_server_result(rv_server_t *s, uint64_t ticket, float *vx, float *vy, floa
         if (f->K > 0 && (vx == nullptr || vy == nullptr || heading == nullptr ||
                          n_inliers == nullptr || status == nullptr))
             return fail(RV_ERR_INVALID_ARG, "a required output is NULL");
+        if (inlier_bits != nullptr && s->cfg.keep_inlier_bits == 0)
+            return fail(RV_ERR_INVALID_ARG, "inlier_bits requested from a server that keeps no masks");
         s->frames.erase(it);
     }
     int rc = RV_OK;
@@ -627,7 +661,10 @@ int rv_server_result(rv_server_t *s, uint64_t ticket, float *vx, float *vy, floa
         memcpy(n_inliers, f->n_inliers.data(), 4 * K);
         memcpy(status, f->status.data(), K);
         if (n_near_tau) memcpy(n_near_tau, f->n_near.data(), 4 * K);
+        if (best_hyp) memcpy(best_hyp, f->best.data(), 4 * K);
     }
+    if (f->state != kFailed && inlier_bits != nullptr && !f->bits.empty())
+        memcpy(inlier_bits, f->bits.data(), 4 * f->bits.size());
     if (times) *times = f->times;
     delete f;
     return rc;

@@ -135,7 +135,9 @@ def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True,
             ref_nearmask = None
             ref_status = st
         else:
-            assert check_hyp, f"cluster {k}: gpu kept h={hg}, oracle h={ho}"
+            # decided from the oracle's bands alone (no GPU counts needed)
+            assert o.hyp_valid is not None, (
+                f"cluster {k}: gpu kept h={hg}, oracle h={ho}, and the oracle ran without bands")
             valid = o.hyp_valid[i].astype(bool)
             clo, chi = o.hyp_count_lo[i], o.hyp_count_hi[i]
             m_lo = clo[valid].max()

@@ -104,6 +104,26 @@ def test_host_argument_checks(lib):
     assert lib.rv_last_error().decode() == ""
 
 
+def test_binding_checks_output_sizes(lib):
+    # Caller-supplied outputs smaller than what the kernels write are refused
+    # on the host (host tensors stand in for device ones: only sizes matter).
+    import torch
+
+    from paper_2012_12618_amd import binding
+
+    cpu = torch.device("cpu")
+    K, N, H = 10, 1000, 256
+    out = binding.allocate_outputs(K, N, H, cpu, want_bits=True, debug=True)
+    assert len(binding._output_ptrs(out, cpu, K, N, H)) == 9
+    for k, n, h, name in ((K, N, 1024, "hyp_counts"), (K + 1, N, H, "vx"),
+                          (K, N + 32, H, "inlier_bits")):
+        with pytest.raises(ValueError, match=name):
+            binding._output_ptrs(out, cpu, k, n, h)
+    out["best_hyp"] = out["best_hyp"][:5]
+    with pytest.raises(ValueError, match="best_hyp"):
+        binding._output_ptrs(out, cpu, K, N, H)
+
+
 def test_philox_hook_argument_checks(lib):
     assert lib.rv_philox4x32_10(None, None, None, -1, None) == -1
     assert lib.rv_philox4x32_10(None, None, None, 0, None) == 0
@@ -176,10 +196,15 @@ def test_server_host_checks(lib):
     cfg = binding.rv_server_config_default()
     assert (cfg.n_hyp, cfg.max_batch_frames, cfg.n_streams) == (512, 64, 2)
     assert cfg.hbm_budget_bytes == 16 << 30
-    # arena bytes of one frame: 36 per point (inputs 8, staging 28) and 65 per cluster
-    # (offsets 4, descriptor 32, best key 8, outputs 21), plus 256-byte sections and queues
+    # arena bytes of one frame: 36 per point (inputs 8, staging 28) and 69 per cluster
+    # (offsets 4, descriptor 32, best key 8, outputs 25), plus 256-byte sections and queues
     b = binding.rv_server_frame_bytes(cfg, 700, 146_000)
-    assert 36 * 146_000 + 65 * 700 <= b <= 36 * 146_000 + 65 * 700 + 24 * 256 + 2560
+    assert 36 * 146_000 + 69 * 700 <= b <= 36 * 146_000 + 69 * 700 + 25 * 256 + 2560
+    # with the inlier masks kept: one more bit per point
+    cfg.keep_inlier_bits = 1
+    bm = binding.rv_server_frame_bytes(cfg, 700, 146_000)
+    assert b + 146_000 // 8 <= bm <= b + 146_000 // 8 + 256
+    cfg.keep_inlier_bits = 0
     assert binding.rv_server_frame_bytes(cfg, -1, 5) == 0
     h = ctypes.c_void_p()
     for field, value, word in (("n_hyp", 0, "n_hyp"), ("tau", 0.0, "tau"),
@@ -198,7 +223,8 @@ def test_server_host_checks(lib):
     t = ctypes.c_uint64()
     assert lib.rv_server_submit(None, None, None, None, 0, 0, 1, ctypes.byref(t)) == -1
     assert lib.rv_server_wait(None, 1, 0) == -1
-    assert lib.rv_server_result(None, 1, None, None, None, None, None, None, None) == -1
+    assert lib.rv_server_result(None, 1, None, None, None, None, None, None, None, None,
+                                None) == -1
     assert lib.rv_server_stats(None, None) == -1
     lib.rv_server_destroy(None)
 

@@ -4,7 +4,8 @@ Acceptance protocol in tests/parity.py.  Cases: the two full-size workloads
 ("small": 64 clusters, H = 256; "dense": 4096 clusters of log-uniform size in
 [8, 4096], H = 1024, the benchmark's launch configuration), random small
 frames over several hypothesis counts, cluster sizes around every register-row
-and register-pass boundary, one 65,536-point cluster, empty and degenerate
+and register-pass boundary, one 65,536-point cluster, a frame of 70,000 small
+clusters (beyond the dispatch planner's limit), empty and degenerate
 clusters, non-finite points and inconsistent offsets; then bitwise invariants
 of the GPU path (power-of-two scaling, sign flip, reflection, determinism,
 independence from the other clusters of the frame) and the device Philox stream.
@@ -110,6 +111,51 @@ def test_parity_one_large_cluster(rv, oracle_mod):
     rng = np.random.default_rng(78)
     th, vd = _cluster(rng, 65536, outlier_frac=0.4)
     _parity(oracle_mod, "large-cluster", th, vd, np.array([0, 65536], np.int32), 128, 0.15, 9)
+
+
+def test_parity_more_clusters_than_the_planner_orders(rv, oracle_mod):
+    # Above 65,536 clusters the single-frame path scores in index order and
+    # refits every cluster with a whole workgroup (no dispatch plan); the
+    # hypothesis thread count grows with the cluster count (Sec. 3.1, Eq. 4).
+    spec = synth.FrameSpec(70000, "uniform", 2, 64, p_uniform=0.2)
+    frame = synth.make_frame(spec, seed=70)
+    H, tau, seed = 64, 0.15, 0x70000
+    g, o, stats = _parity(oracle_mod, "70k-clusters", frame.theta, frame.vd, frame.offsets, H, tau,
+                          seed)
+    assert stats["clusters"] == 70000
+    # the same frame through the batched entry point: bitwise the same outputs
+    dev = "cuda:0"
+    t = torch.from_numpy(frame.theta).to(dev)
+    v = torch.from_numpy(frame.vd).to(dev)
+    off = torch.from_numpy(frame.offsets).to(dev)
+    fo = torch.tensor([0, frame.n_clusters], dtype=torch.int32, device=dev)
+    seeds = torch.tensor([seed], dtype=torch.int64, device=dev)
+    print(f"[gpu] rv_estimate_velocity_batch 70k-clusters K={frame.n_clusters} H={H}", flush=True)
+    b = rv.rv_estimate_velocity_batch(t, v, off, fo, seeds, H, tau, want_bits=True, debug=True)
+    torch.cuda.synchronize()
+    for name in ("vx", "vy", "heading", "n_inliers", "status", "n_near_tau", "best_hyp",
+                 "hyp_counts", "inlier_bits"):
+        got = b[name].cpu().numpy()
+        assert np.array_equal(got, g[name], equal_nan=name in ("vx", "vy", "heading")), name
+
+
+def test_reused_outputs_too_small_are_refused(rv):
+    # Outputs allocated for H = 256 reused with H = 1024, or for a smaller
+    # frame: the binding raises before any launch.
+    frame, H, tau = synth.make_workload("small")
+    dev = torch.device("cuda:0")
+    t = torch.from_numpy(frame.theta).to(dev)
+    v = torch.from_numpy(frame.vd).to(dev)
+    off = torch.from_numpy(frame.offsets).to(dev)
+    out = rv.allocate_outputs(frame.n_clusters, frame.n_points, 256, dev, debug=True)
+    with pytest.raises(ValueError, match="hyp_counts"):
+        rv.rv_estimate_velocity(t, v, off, 1024, tau, 1, out=out)
+    small = rv.allocate_outputs(frame.n_clusters - 1, frame.n_points, 256, dev)
+    with pytest.raises(ValueError, match="vx"):
+        rv.rv_estimate_velocity(t, v, off, 256, tau, 1, out=small)
+    ok = rv.rv_estimate_velocity(t, v, off, 256, tau, 1, out=out)
+    torch.cuda.synchronize()
+    assert int((ok["status"] == 0).sum()) > 0
 
 
 def test_parity_narrow_azimuth_clusters(rv, oracle_mod):
