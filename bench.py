@@ -157,6 +157,46 @@ def profiled_valu_issue(workload: str):
             "clock_ghz": cycles / (rec["kernel_us"] * 1e3), "source": os.path.basename(path)}
 
 
+def host_cpus() -> dict:
+    """What the host offers this process: logical CPUs (nproc), the affinity
+    mask, the cgroup CPU quota, the thread-count environment and the CPU model."""
+    info = {"nproc": os.cpu_count(), "affinity": None, "cgroup_quota_cpus": None,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS") or None, "model": None}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            info["cgroup_quota_cpus"] = int(quota) / int(period)
+    except (OSError, ValueError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return info
+
+
+def oracle_threads(args) -> int:
+    """Oracle threads: --cpu-threads, else every CPU this process may use (the
+    affinity mask, bounded by the cgroup quota and by OMP_NUM_THREADS, which
+    the host sets to this job's CPU share)."""
+    if args.cpu_threads:
+        return args.cpu_threads
+    info = host_cpus()
+    n = info["affinity"] or info["nproc"] or 1
+    if info["cgroup_quota_cpus"]:
+        n = min(n, max(1, int(info["cgroup_quota_cpus"])))
+    if info["omp_num_threads"] and info["omp_num_threads"].isdigit():
+        n = min(n, max(1, int(info["omp_num_threads"])))
+    return n
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -202,7 +242,74 @@ def sum_evals(frame, n_hyp):
     return synth.evals_per_frame(frame.offsets, n_hyp)
 
 
-def batch_bench(args, torch, binding, synth, dev) -> int:
+def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_frames):
+    """Host-clock latency of n_frames distinct frames, each from pinned host
+    memory through the H2D copies, the estimate and the D2H copies of the
+    per-cluster results (synchronised per frame).  Frame i is drawn fresh for
+    the small workload (data seed 100000 + i); for the dense one, whose frames
+    are 22 MB each, it is base frame i % 8 (the benchmark frame and seven more
+    draws) with every azimuth turned by a distinct angle of at most 0.062 rad,
+    so that no two timed frames are equal.  Each frame is written into the
+    pinned buffer before its clock starts.  Returns (milliseconds per frame,
+    recipe text)."""
+    import numpy as np
+
+    if n_frames <= 0:
+        return [], None
+    spec = synth.WORKLOADS[name][0]
+    if name == "small":
+        bases = [synth.make_frame(spec, 100_000 + i) for i in range(n_frames)]
+        recipe = f"{n_frames} frames drawn with data seeds 100000.. (all distinct)"
+
+        def frame_at(i):
+            f = bases[i]
+            return f.theta, f.vd, f.offsets
+    else:
+        bases = [frame] + [synth.make_frame(spec, 1000 + f) for f in range(7)]
+        recipe = ("8 drawn frames (the benchmark frame, data seeds 1000..1006), frame i = base "
+                  "i % 8 with every azimuth turned by ((i // 8) - 62) * 1e-3 rad (float32 add)")
+
+        def frame_at(i):
+            f = bases[i % len(bases)]
+            phi = np.float32(((i // len(bases)) - 62) * 1e-3)
+            return f.theta + phi, f.vd, f.offsets
+    n_max = max(f.n_points for f in bases)
+    k_max = max(f.n_clusters for f in bases)
+    h_t = torch.empty(n_max, dtype=torch.float32).pin_memory()
+    h_v = torch.empty(n_max, dtype=torch.float32).pin_memory()
+    h_o = torch.empty(k_max + 1, dtype=torch.int32).pin_memory()
+    d_t = torch.empty(n_max, dtype=torch.float32, device=dev)
+    d_v = torch.empty(n_max, dtype=torch.float32, device=dev)
+    d_o = torch.empty(k_max + 1, dtype=torch.int32, device=dev)
+    out = binding.allocate_outputs(k_max, n_max, n_hyp, dev, want_near=True)
+    keys = ("vx", "vy", "heading", "n_inliers", "status")
+    res = {k: torch.empty(out[k].shape, dtype=out[k].dtype).pin_memory() for k in keys}
+
+    def one(i, seed):
+        th, vd, off = frame_at(i)
+        n, k = th.shape[0], off.shape[0] - 1
+        h_t[:n].numpy()[:] = th
+        h_v[:n].numpy()[:] = vd
+        h_o[:k + 1].numpy()[:] = off
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d_t[:n].copy_(h_t[:n], non_blocking=True)
+        d_v[:n].copy_(h_v[:n], non_blocking=True)
+        d_o[:k + 1].copy_(h_o[:k + 1], non_blocking=True)
+        binding.rv_estimate_velocity(d_t[:n], d_v[:n], d_o[:k + 1], n_hyp, tau, seed, out=out,
+                                     stream=stream)
+        for key in keys:
+            res[key][:k].copy_(out[key][:k], non_blocking=True)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    for i in range(min(8, n_frames)):  # untimed first use of the buffers
+        one(i, synth.ransac_seed(name, 9_000 + i))
+    lat = [one(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    return lat, recipe
+
+
+def batch_bench(args, torch, binding, synth, dev) -> dict:
     """Batched form: every step replays one captured graph over all frames."""
     name = args.workload
     print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)
@@ -291,7 +398,7 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = oracle_threads(args)
         print(f"[bench] oracle on the host, {threads} threads", file=sys.stderr, flush=True)
         sample = [batch.frame_slice(f) for f in range(min(F, 8))]
         done, dt, ev_done, cl_done = oracle_baseline(
@@ -299,7 +406,7 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
         cpu = {"value": ev_done / dt, "unit": "hyp-point evals/s", "cores": threads, "kind": "oracle",
                "sample": (f"{done} whole frame(s) of the batch ({cl_done} clusters, {ev_done} evals), "
                           f"FP64, {dt:.2f} s wall on {threads} threads"),
-               "clusters_per_s": cl_done / dt}
+               "clusters_per_s": cl_done / dt, "host": host_cpus()}
 
     sec = ms_per_step / 1e3
     line = {
@@ -335,11 +442,10 @@ def batch_bench(args, torch, binding, synth, dev) -> int:
                      "kernel_ms": score_ms},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
-def served_bench(args, torch, binding, synth, dev) -> int:
+def served_bench(args, torch, binding, synth, dev) -> dict:
     """Served form: paced arrivals for latency, then the same frames as fast as
     the server takes them for throughput; the per-frame form (one frame per
     launch, one slot) on the same traffic for comparison."""
@@ -404,14 +510,14 @@ def served_bench(args, torch, binding, synth, dev) -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = oracle_threads(args)
         print(f"[bench] oracle on the host, {threads} threads", file=sys.stderr, flush=True)
         done, dt, ev_done, cl_done = oracle_baseline(
             frames[:8], n_hyp, tau, lambda i: synth.frame_seed(name, 90_000 + i), threads)
         cpu = {"value": ev_done / dt, "unit": "hyp-point evals/s", "cores": threads, "kind": "oracle",
                "sample": (f"{done} radar frame(s) ({cl_done} clusters, {ev_done} evals), FP64, "
                           f"{dt:.2f} s wall on {threads} threads"),
-               "clusters_per_s": cl_done / dt}
+               "clusters_per_s": cl_done / dt, "host": host_cpus()}
 
     def brief(paced_sum, sat_sum):
         return {"latency_ms": paced_sum["latency_ms"], "server_latency_ms": paced_sum["server_latency_ms"],
@@ -454,8 +560,7 @@ def served_bench(args, torch, binding, synth, dev) -> int:
                      "kernel_ms": score_ms_total / max(n_calls, 1), "launches": n_calls},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
 def paper_sweep_bench(args, torch, binding, synth, dev) -> int:
@@ -609,7 +714,7 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
     # Error of every result against the FP64 oracle, over clusters taken in
     # rounds of `threads` spread across the frame until about 10 s of oracle
     # wall time (or all of them); the same runs are the CPU baseline.
-    threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    threads = oracle_threads(args)
     order = [k for r in range(max(1, K // threads)) for k in range(r, K, max(1, K // threads))]
     ids, dt, rounds = [], 0.0, []
     g = forms["fp16"]["res"]
@@ -635,7 +740,8 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
     cpu = None if args.no_cpu_baseline else {
         "value": ev_sample / dt, "unit": "hyp-point evals/s", "cores": min(threads, len(ids)),
         "kind": "oracle",
-        "sample": f"{len(ids)} clusters of 65,536 points x 4096 hypotheses, FP64, {dt:.2f} s wall"}
+        "sample": f"{len(ids)} clusters of 65,536 points x 4096 hypotheses, FP64, {dt:.2f} s wall",
+        "host": host_cpus()}
 
     f16, f32 = forms["fp16"], forms["fp32"]
     score16 = f16["stage_ms"]["score"]
@@ -704,70 +810,10 @@ def host_comparators(f, H):
     return out
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--min-warmup-ms", type=float, default=100.0,
-                    help="after the warm-up steps, more untimed steps until this much time has passed")
-    ap.add_argument("--workload", default="dense", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--latency-frames", type=int, default=1000,
-                    help="frames timed from pinned host memory to results in host memory")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: min(16, cpus))")
-    ap.add_argument("--frames", type=int, default=0,
-                    help="batched workload: number of frames (0: the workload's 256)")
-    ap.add_argument("--submitters", type=int, default=4,
-                    help="served workload: threads submitting frames (radars dealt round-robin)")
-    ap.add_argument("--duration", type=float, default=5.0,
-                    help="served workload: seconds of simulated arrivals in the timed run")
-    ap.add_argument("--host-comparators", action="store_true",
-                    help="paper-sweep: also time scikit-learn RANSACRegressor and numpy pinv per "
-                         "cluster on the host (the paper's Table I/II comparators; context only)")
-    ap.add_argument("--tuning", default="",
-                    help="batched workload: JSON tuning table written by paper_2012_12618_amd.tuner "
-                         "(default: the library's default setting)")
-    ap.add_argument("--stage-sample-every", type=int, default=10,
-                    help="frame workloads: record the library's per-kernel events on every n-th "
-                         "timed step (1: every step)")
-    ap.add_argument("--fp16-min-points", type=int, default=0,
-                    help="batched and precision workloads: clusters of at least this many points "
-                         "take the FP16 residual form (precision default: 1024; batched default: "
-                         "none)")
-    ap.add_argument("--copy-calibration-mb", type=int, default=0,
-                    help="also run one device-to-device copy of this many MiB (outside the timed "
-                         "region), the reference kernel for scaling HBM byte counters")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print(f"bench.py: this estimator runs on one GPU (asked for --gpus {args.gpus}); clusters are "
-              "independent, so a multi-GPU deployment shards frames or clusters without any "
-              "collective and its throughput is the sum of single-GPU runs.", file=sys.stderr)
-        return 2
-    if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
-        print("bench.py: run on a single rank", file=sys.stderr)
-        return 2
-
+def frame_bench(args, torch, binding, synth, dev, name) -> dict:
+    """One frame resident in HBM, estimated step after step (dense or small)."""
     import numpy as np
-    import torch
 
-    from paper_2012_12618_amd import binding, synth
-
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        return 1
-    binding.load_library()
-    dev = torch.device("cuda:0")
-    name = args.workload
-    if name == "served":
-        return served_bench(args, torch, binding, synth, dev)
-    if name == "paper-sweep":
-        return paper_sweep_bench(args, torch, binding, synth, dev)
-    if name == "precision":
-        return precision_bench(args, torch, binding, synth, dev)
-    if name not in FRAME_WORKLOADS:
-        return batch_bench(args, torch, binding, synth, dev)
     print(f"[bench] generating {name} workload", file=sys.stderr, flush=True)
     frame, n_hyp, tau = synth.make_workload(name)
     K, N = frame.n_clusters, frame.n_points
@@ -834,43 +880,9 @@ def main() -> int:
     kernel = "small_frame_kernel" if small_path else "score_kernel"
 
     # Frame latency: pinned host frame -> device -> estimate -> results in host memory.
-    print(f"[bench] latency over {args.latency_frames} frames", file=sys.stderr, flush=True)
-    n_distinct = 8
-    frames = [frame] + [synth.make_frame(synth.WORKLOADS[name][0], 1000 + f)
-                        for f in range(n_distinct - 1)]
-    slots = []
-    for f in frames:
-        h = tuple(torch.from_numpy(a).pin_memory() for a in (f.theta, f.vd, f.offsets))
-        d = tuple(torch.empty(a.shape, dtype=a.dtype, device=dev) for a in h)
-        o = binding.allocate_outputs(f.n_clusters, f.n_points, n_hyp, dev, want_near=True)
-        r = {k: torch.empty(o[k].shape, dtype=o[k].dtype).pin_memory()
-             for k in ("vx", "vy", "heading", "n_inliers", "status")}
-        slots.append((h, d, o, r))
-    lat = []
-    for i in range(len(slots) if args.latency_frames else 0):  # untimed first use of each slot
-        (h_t, h_v, h_o), (d_t, d_v, d_o), o2, r = slots[i]
-        d_t.copy_(h_t, non_blocking=True)
-        d_v.copy_(h_v, non_blocking=True)
-        d_o.copy_(h_o, non_blocking=True)
-        binding.rv_estimate_velocity(d_t, d_v, d_o, n_hyp, tau, synth.ransac_seed(name, 9_000 + i),
-                                     out=o2, stream=stream)
-        for k, hbuf in r.items():
-            hbuf.copy_(o2[k], non_blocking=True)
-    torch.cuda.synchronize()
-    for i in range(args.latency_frames):
-        (h_t, h_v, h_o), (d_t, d_v, d_o), o2, r = slots[i % len(slots)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        d_t.copy_(h_t, non_blocking=True)
-        d_v.copy_(h_v, non_blocking=True)
-        d_o.copy_(h_o, non_blocking=True)
-        binding.rv_estimate_velocity(d_t, d_v, d_o, n_hyp, tau, synth.ransac_seed(name, 10_000 + i),
-                                     out=o2, stream=stream)
-        for k, hbuf in r.items():
-            hbuf.copy_(o2[k], non_blocking=True)
-        torch.cuda.synchronize()
-        lat.append((time.perf_counter() - t0) * 1e3)
-    del slots
+    print(f"[bench] latency over {args.latency_frames} distinct frames", file=sys.stderr, flush=True)
+    lat, lat_recipe = latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau,
+                                  args.latency_frames)
 
     calibration_copy(torch, dev, args.copy_calibration_mb)
 
@@ -878,7 +890,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         import oracle
 
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = oracle_threads(args)
         print(f"[bench] oracle on the host, {threads} threads", file=sys.stderr, flush=True)
         # Whole frames with fresh hypothesis seeds until about 1.5 s of wall time.
         frames_done, dt = 0, 0.0
@@ -893,7 +905,7 @@ def main() -> int:
                "kind": "oracle",
                "sample": (f"{frames_done} whole {name} frame(s) ({K} clusters, {evals} evals each, "
                           f"fresh seeds), FP64, {dt:.2f} s wall on {threads} threads"),
-               "clusters_per_s": frames_done * K / dt}
+               "clusters_per_s": frames_done * K / dt, "host": host_cpus()}
         # One thread on every 8th cluster of the frame.
         ids = np.arange(0, K, 8)
         sizes = np.diff(frame.offsets.astype(np.int64))[ids]
@@ -927,7 +939,7 @@ def main() -> int:
         "clusters_per_s": clusters_per_s,
         "frac_fp32_valu_peak": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
         "latency_ms": ({"p50": percentile(lat, 50), "p99": percentile(lat, 99), "frames": len(lat),
-                        "distinct_frames": len(frames),
+                        "distinct_frames": len(lat), "frames_recipe": lat_recipe,
                         "scope": "pinned host frame -> H2D -> estimate -> D2H of per-cluster results"}
                        if lat else None),
         "step_ms": {"median": percentile(step_times, 50), "p99": percentile(step_times, 99),
@@ -943,6 +955,134 @@ def main() -> int:
                      "valu_issue": profiled_valu_issue(name) if kernel == "score_kernel" else None},
         "cpu_baseline": cpu,
     }
+    return line
+
+
+def default_extras(args, torch, binding, synth, dev) -> dict:
+    """The other workloads' headline figures for the default (dense) line, so
+    that one run reports them all: the small frame (the paper's Table I shape:
+    per-step time and latency over 1000 distinct frames), the 256-frame batched
+    form (one graph replay per step, and the per-frame form on the same
+    frames), and the served form at 64 radars x 20 frames/s (latency and
+    saturated throughput of the served and the per-frame forms)."""
+    import copy
+
+    out = {}
+    a = copy.copy(args)
+    a.no_cpu_baseline = True
+    a.steps = max(20, min(args.steps, 200))
+    small = frame_bench(a, torch, binding, synth, dev, "small")
+    out["small_frame"] = {
+        "workload": WORKLOAD_TEXT["small"], "ms_per_step": small["ms_per_step"],
+        "clusters_per_s": small["clusters_per_s"], "evals_per_s": small["value"],
+        "latency_ms": small["latency_ms"], "kernel": small["roofline"]["kernel"],
+        "kernel_ms": small["roofline"]["kernel_ms"]}
+    a = copy.copy(args)
+    a.no_cpu_baseline = True
+    a.workload = "batched"
+    a.steps = max(5, min(args.steps, 20))
+    a.warmup = 3
+    b = batch_bench(a, torch, binding, synth, dev)
+    out["batched"] = {
+        "workload": WORKLOAD_TEXT["batched"], "ms_per_step": b["ms_per_step"],
+        "clusters_per_s": b["clusters_per_s"], "evals_per_s": b["value"],
+        "frames": b["config"]["frames"], "clusters": b["config"]["clusters"],
+        "frac_fp32_valu_peak": b["frac_fp32_valu_peak"], "stage_ms": b["stage_ms"],
+        "per_frame_form": b["per_frame_form"],
+        "batched_over_per_frame_clusters_per_s":
+            b["clusters_per_s"] / b["per_frame_form"]["clusters_per_s"]}
+    a = copy.copy(args)
+    a.no_cpu_baseline = True
+    a.workload = "served"
+    a.duration = args.extras_duration
+    sv = served_bench(a, torch, binding, synth, dev)
+    out["served"] = {
+        "workload": WORKLOAD_TEXT["served"], "duration_s": a.duration,
+        "arrivals": sv["config"]["frames"], "served_form": sv["served_form"],
+        "per_frame_form": sv["per_frame_form"],
+        "served_over_per_frame_clusters_per_s":
+            sv["served_form"]["saturated"]["clusters_per_s"]
+            / sv["per_frame_form"]["saturated"]["clusters_per_s"],
+        "p99_served_over_per_frame":
+            sv["served_form"]["latency_ms"]["p99"] / sv["per_frame_form"]["latency_ms"]["p99"]}
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--min-warmup-ms", type=float, default=100.0,
+                    help="after the warm-up steps, more untimed steps until this much time has passed")
+    ap.add_argument("--workload", default="dense", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--latency-frames", type=int, default=1000,
+                    help="frames timed from pinned host memory to results in host memory")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads (0: every CPU this process may use, see oracle_threads)")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="batched workload: number of frames (0: the workload's 256)")
+    ap.add_argument("--submitters", type=int, default=4,
+                    help="served workload: threads submitting frames (radars dealt round-robin)")
+    ap.add_argument("--duration", type=float, default=5.0,
+                    help="served workload: seconds of simulated arrivals in the timed run")
+    ap.add_argument("--host-comparators", action="store_true",
+                    help="paper-sweep: also time scikit-learn RANSACRegressor and numpy pinv per "
+                         "cluster on the host (the paper's Table I/II comparators; context only)")
+    ap.add_argument("--tuning", default="",
+                    help="batched workload: JSON tuning table written by paper_2012_12618_amd.tuner "
+                         "(default: the library's default setting)")
+    ap.add_argument("--stage-sample-every", type=int, default=10,
+                    help="frame workloads: record the library's per-kernel events on every n-th "
+                         "timed step (1: every step)")
+    ap.add_argument("--fp16-min-points", type=int, default=0,
+                    help="batched and precision workloads: clusters of at least this many points "
+                         "take the FP16 residual form (precision default: 1024; batched default: "
+                         "none)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="dense workload: skip the small, batched and served figures that the "
+                         "default line carries")
+    ap.add_argument("--extras-duration", type=float, default=3.0,
+                    help="seconds of simulated arrivals for the served figures of the default line")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (outside the timed "
+                         "region), the reference kernel for scaling HBM byte counters")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this estimator runs on one GPU (asked for --gpus {args.gpus}); clusters are "
+              "independent, so a multi-GPU deployment shards frames or clusters without any "
+              "collective and its throughput is the sum of single-GPU runs.", file=sys.stderr)
+        return 2
+    if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
+        print("bench.py: run on a single rank", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2012_12618_amd import binding, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    binding.load_library()
+    dev = torch.device("cuda:0")
+    name = args.workload
+    if name == "served":
+        print(json.dumps(served_bench(args, torch, binding, synth, dev)), flush=True)
+        return 0
+    if name == "paper-sweep":
+        return paper_sweep_bench(args, torch, binding, synth, dev)
+    if name == "precision":
+        return precision_bench(args, torch, binding, synth, dev)
+    if name not in FRAME_WORKLOADS:
+        line = batch_bench(args, torch, binding, synth, dev)
+    else:
+        line = frame_bench(args, torch, binding, synth, dev, name)
+        if name == "dense" and not args.no_extras:
+            line.update(default_extras(args, torch, binding, synth, dev))
     print(json.dumps(line), flush=True)
     return 0
 

@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
         return _LIB
     tmp = _LIB + ".tmp"
     cmd = [
-        "gcc", "-O2", "-march=x86-64-v2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        "gcc", "-O3", "-march=x86-64-v3", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
         "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, _SRC_PAPER, "-lm", "-lpthread",
     ]
     subprocess.run(cmd, check=True)
