@@ -22,7 +22,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rv_oracle.c")
 _SRC_PAPER = os.path.join(_HERE, "rv_oracle_paper.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# RV_ORACLE_LIB names another build of the same sources (the sanitizer check
+# in check_sanitizers.sh loads an ASan/UBSan build this way).
+_LIB = os.environ.get("RV_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 # Per-cluster status codes (same meaning as the estimator's).
 CLUSTER_OK = 0
