@@ -148,10 +148,17 @@ typedef struct {
        float32 form, so every output is bitwise the same, except hyp_counts:
        there it holds the FP16 counts, upper bounds of the float32 counts. */
     int32_t fp16_min_points;
+    /* clusters of at most this many points (0..256) score with lanes =
+       hypotheses: each thread keeps the hypothesis it solved, the cluster's
+       points are staged in LDS and read as broadcasts, and each lane counts its
+       own inliers (four vector instructions per point and 64 hypotheses, no
+       lanes idle for a cluster smaller than 64 points).  Same arithmetic, so
+       the same results bit for bit; it takes precedence over the FP16 form. */
+    int32_t lanes_max_points;
 } rv_tuning_t;
 
 /* Defaults: 16 rows in every bucket, as many workgroups per CU as fit, no
-   FP16 form. */
+   FP16 form, lanes = hypotheses for clusters of at most 64 points. */
 void rv_tuning_default(rv_tuning_t *tuning);
 
 /* Device workspace bytes of rv_estimate_velocity_batch (0 for invalid sizes). */

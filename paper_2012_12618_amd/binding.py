@@ -43,23 +43,26 @@ _lib = None
 
 class RVTuning(ctypes.Structure):
     """rv_tuning_t: register rows per pass for each cluster-size bucket, the
-    persistent grid's workgroups per compute unit (0: as many as fit) and the
-    smallest cluster scored in the FP16 residual form (0: none)."""
+    persistent grid's workgroups per compute unit (0: as many as fit), the
+    smallest cluster scored in the FP16 residual form (0: none) and the largest
+    cluster scored with lanes = hypotheses."""
 
     _fields_ = [("rows_max", ctypes.c_int32 * RV_TUNE_BUCKETS), ("blocks_per_cu", ctypes.c_int32),
-                ("fp16_min_points", ctypes.c_int32)]
+                ("fp16_min_points", ctypes.c_int32), ("lanes_max_points", ctypes.c_int32)]
 
     def to_dict(self) -> dict:
         return {"rows_max": list(self.rows_max), "blocks_per_cu": int(self.blocks_per_cu),
-                "fp16_min_points": int(self.fp16_min_points)}
+                "fp16_min_points": int(self.fp16_min_points),
+                "lanes_max_points": int(self.lanes_max_points)}
 
     @classmethod
     def from_dict(cls, d: dict) -> "RVTuning":
-        t = cls()
+        t = rv_tuning_default()
         for i, r in enumerate(d["rows_max"]):
             t.rows_max[i] = int(r)
         t.blocks_per_cu = int(d.get("blocks_per_cu", 0))
         t.fp16_min_points = int(d.get("fp16_min_points", 0))
+        t.lanes_max_points = int(d.get("lanes_max_points", t.lanes_max_points))
         return t
 
 

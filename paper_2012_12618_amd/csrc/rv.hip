@@ -576,6 +576,86 @@ __device__ __forceinline__ unsigned long long hyp_key(uint32_t count, int64_t h)
     return ((unsigned long long)count << 32) | (0xFFFFFFFFull - (uint32_t)h);
 }
 
+// ---------------------------------------------------------------------------
+// Small clusters with lanes = hypotheses (batched form, clusters of at most
+// Tuning::lanes_max points, at most kLaneTile).  With lanes = points a cluster
+// of n < 64 points leaves 64 - n lanes of every compare idle; here each thread
+// keeps the hypothesis it solved in registers, the cluster's points are staged
+// in LDS and read by every lane at the same address (a broadcast), and each
+// lane counts its own inliers with one compare and one add per point: four
+// vector instructions per point and 64 hypotheses, none on the scalar unit.
+// The residual and the test are the float32 loop's, fma(-hy, s, fma(-hx, c,
+// v_d)) and |.| < tau, so every count, and the block's key, is the same bit for
+// bit.
+// ---------------------------------------------------------------------------
+
+constexpr int kLaneTile = 256;        // points staged in LDS: the largest cluster of this form
+constexpr int kDefaultLanesMax = 64;  // default Tuning::lanes_max
+
+struct LaneShared {
+    float4 c[kLaneTile / 4], s[kLaneTile / 4], v[kLaneTile / 4];  // padded with (0, 0, +inf)
+    unsigned long long key[kScoreBlock / kWave];
+};
+
+// One scoring block of a cluster with 2 <= n <= kLaneTile points, lanes =
+// hypotheses.  Called by all threads of the block from the persistent loop
+// (every branch around a barrier is on a wave-uniform value).
+__device__ __forceinline__ void score_block_lanes(Span sp, ClusterId id, int b, int32_t n_hyp,
+                                                  const Points &pts, float tau, LaneShared &sh,
+                                                  unsigned long long *__restrict__ best_key,
+                                                  int32_t *__restrict__ hyp_counts) {
+    const int tid = threadIdx.x;
+    const int n = (int)sp.n;
+    const int n4 = (n + 3) / 4;
+    if (tid < 4 * n4) {  // a padding point: e = +inf, never below tau
+        float c = 0.0f, sn = 0.0f, v = __builtin_inff();
+        if (tid < n) {
+            const float2 q = pts.cs32[sp.lo + tid];
+            c = q.x;
+            sn = q.y;
+            v = pts.v32[sp.lo + tid];
+        }
+        reinterpret_cast<float *>(sh.c)[tid] = c;
+        reinterpret_cast<float *>(sh.s)[tid] = sn;
+        reinterpret_cast<float *>(sh.v)[tid] = v;
+    }
+    const int64_t h = (int64_t)b * kScoreBlock + tid;
+    float hx = __builtin_nanf(""), hy = __builtin_nanf("");
+    if (h < n_hyp) {
+        const Hypothesis hyp = make_hypothesis(pts, sp, (uint32_t)h, id.local, id.key0, id.key1);
+        hx = (float)hyp.vx;  // NaN exactly when the pair is degenerate: counts 0
+        hy = (float)hyp.vy;
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = tid % kWave;
+    uint32_t cnt = 0;
+    for (int q = 0; q < n4; ++q) {
+        const float4 c = sh.c[q], sn = sh.s[q], v = sh.v[q];
+        const float cc[4] = {c.x, c.y, c.z, c.w}, ss[4] = {sn.x, sn.y, sn.z, sn.w};
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float e = __builtin_fmaf(-hy, ss[u], __builtin_fmaf(-hx, cc[u], vv[u]));
+            cnt += __builtin_fabsf(e) < tau ? 1u : 0u;
+        }
+    }
+    unsigned long long key = 0;
+    if (h < n_hyp) {
+        if (hyp_counts != nullptr) hyp_counts[id.out * n_hyp + h] = (int32_t)cnt;
+        if (!__builtin_isnan(hx)) key = hyp_key(cnt, h);
+    }
+    key = wave_max_u64(key);
+    if (lane == 0) sh.key[wave] = key;
+    __syncthreads();
+    if (wave == 0) {  // wave-uniform guard; one lane merges the block's key
+        for (int w = 1; w < kScoreBlock / kWave; ++w) key = sh.key[w] > key ? sh.key[w] : key;
+        if (lane == 0 && key != 0) atomicMax(&best_key[id.out], key);
+    }
+    // The next item restages the tile only after the work-queue fetch's two
+    // block barriers, which every wave reaches after its last read of it.
+}
+
 // Exact float32 counts of the nl (<= 64) hypotheses in sh.list over the whole
 // cluster; wave w scores rows [w rows/4, (w+1) rows/4) of the cluster.  Lane q
 // of every wave returns the count of list entry q.  Contains barriers.
@@ -1080,8 +1160,12 @@ struct Batch {
 // bucket b holds n in [32 * 2^b, 64 * 2^b), the last bucket everything larger.
 struct Tuning {
     int32_t rows[RV_TUNE_BUCKETS];
-    int32_t fp16_min;  // clusters of at least this many points use the FP16 form; 0: none
+    int32_t fp16_min;   // clusters of at least this many points use the FP16 form; 0: none
+    int32_t lanes_max;  // clusters of at most this many points score with lanes = hypotheses
 };
+
+// Scoring form of a cluster (ItemDesc::form).
+enum : int16_t { kFormRows = 0, kFormFp16 = 1, kFormLanes = 2 };
 
 // Everything the scoring and refit workgroups need about one cluster, at its
 // position in the dispatch order: one 32-byte load instead of a chain of
@@ -1093,7 +1177,7 @@ struct alignas(32) ItemDesc {
     uint32_t key0, key1;   // Philox key: its frame's seed
     int32_t ok;            // offsets valid
     int16_t rows;          // register rows per pass for its size
-    int16_t fp16;          // scored in the FP16 residual form
+    int16_t form;          // kFormRows, kFormFp16 or kFormLanes
 };
 
 constexpr int kQueueStride = 32;  // 64-bit counters: 256 bytes between queues
@@ -1217,7 +1301,11 @@ __global__ __launch_bounds__(kPrepBlock) void batch_scatter_kernel(
     d.key1 = (uint32_t)(seed >> 32);
     d.ok = sp.ok ? 1 : 0;
     d.rows = (int16_t)tune.rows[size_bucket(sp.n)];
-    d.fp16 = (int16_t)(tune.fp16_min > 0 && sp.ok && sp.n >= 2 && sp.n >= tune.fp16_min ? 1 : 0);
+    d.form = kFormRows;
+    if (sp.ok && sp.n >= 2 && sp.n <= tune.lanes_max)
+        d.form = kFormLanes;
+    else if (tune.fp16_min > 0 && sp.ok && sp.n >= 2 && sp.n >= tune.fp16_min)
+        d.form = kFormFp16;
     desc[base[cls] + rank] = d;
 }
 
@@ -1241,6 +1329,7 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(kFp
     __shared__ unsigned long long s_key[kScoreBlock / kWave];
     __shared__ unsigned long long s_item;
     __shared__ Fp16Shared s_fp16;  // unreferenced, so not allocated, when !kFp16
+    __shared__ LaneShared s_lanes;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const uint32_t home = blockIdx.x % kXcds;
@@ -1262,8 +1351,13 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(kFp
             const int64_t j = (int64_t)q + (int64_t)kXcds * (int64_t)(item / bpc);
             const int b = (int)(item % bpc);
             const ItemDesc d = desc[j];
+            if (d.form == kFormLanes) {
+                score_block_lanes(desc_span(d), desc_id(d), b, n_hyp, pts, tau, s_lanes, best_key,
+                                  hyp_counts);
+                continue;
+            }
             if constexpr (kFp16) {
-                if (d.fp16 != 0) {
+                if (d.form == kFormFp16) {
                     score_block_fp16(desc_span(d), desc_id(d), b, n_hyp, pts, tau, d.rows, s_fp16,
                                      best_key, hyp_counts);
                     continue;
@@ -1406,6 +1500,8 @@ int check_batch(const BatchArgs &a) {
         return fail(RV_ERR_INVALID_ARG, "tuning.blocks_per_cu must be in [0, 64]");
     if (a.tuning.fp16_min_points < 0)
         return fail(RV_ERR_INVALID_ARG, "tuning.fp16_min_points must be >= 0");
+    if (a.tuning.lanes_max_points < 0 || a.tuning.lanes_max_points > kLaneTile)
+        return fail(RV_ERR_INVALID_ARG, "tuning.lanes_max_points must be in [0, %d]", kLaneTile);
     const BatchLayout L = make_batch_layout(a.n_clusters, a.n_points);
     if (a.workspace == nullptr || a.workspace_bytes < L.total)
         return fail(RV_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", L.total,
@@ -1490,6 +1586,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     Tuning tune;
     for (int b = 0; b < RV_TUNE_BUCKETS; ++b) tune.rows[b] = a.tuning.rows_max[b];
     tune.fp16_min = a.tuning.fp16_min_points;
+    tune.lanes_max = a.tuning.lanes_max_points;
     const int64_t bpc = batch_blocks_per_cluster(a);
     const int64_t n_words = a.o.bits != nullptr ? (a.n_points + 31) / 32 : 0;
     int64_t prep_items = a.n_points > n_words ? a.n_points : n_words;
@@ -1750,6 +1847,7 @@ void rv_tuning_default(rv_tuning_t *t) {
     for (int b = 0; b < RV_TUNE_BUCKETS; ++b) t->rows_max[b] = kRowsMax;
     t->blocks_per_cu = 0;
     t->fp16_min_points = 0;
+    t->lanes_max_points = kDefaultLanesMax;
 }
 
 size_t rv_batch_workspace_bytes(int64_t n_frames, int64_t n_clusters, int64_t n_points,

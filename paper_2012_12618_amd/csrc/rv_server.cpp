@@ -459,6 +459,8 @@ int check_config(const rv_server_config_t *c) {
         return fail(RV_ERR_INVALID_ARG, "tuning.blocks_per_cu must be in [0, 64]");
     if (c->tuning.fp16_min_points < 0)
         return fail(RV_ERR_INVALID_ARG, "tuning.fp16_min_points must be >= 0");
+    if (c->tuning.lanes_max_points < 0 || c->tuning.lanes_max_points > 256)
+        return fail(RV_ERR_INVALID_ARG, "tuning.lanes_max_points must be in [0, 256]");
     return RV_OK;
 }
 

@@ -10,10 +10,14 @@ never a result bit:
   wasted in the last, partial pass of a cluster.
 * ``blocks_per_cu``: workgroups of the persistent scoring grid per compute
   unit (0: as many as fit).
-
-Hypotheses per wave are fixed at 64 (one per lane, which is where the wave's
-inlier count of each hypothesis lands), so the tile the tuner picks is the
-point tile.
+* ``lanes_max_points``: the orientation of the scoring loop by cluster size.
+  Clusters of at most this many points score with lanes = hypotheses (each
+  lane counts its own inliers over the cluster's points, read from LDS as
+  broadcasts: 64 hypotheses per wave instruction whatever the cluster size);
+  larger ones with lanes = points (each wave instruction tests one
+  hypothesis against 64 points, and the last row of a cluster leaves lanes
+  idle).  This is the hypotheses-per-wave knob: 64 hypotheses per
+  instruction below the threshold, one above.
 
 The tuner times whole batched calls on the caller's own inputs (coordinate
 descent: one bucket at a time, then the grid), keeps the fastest setting per
@@ -34,6 +38,7 @@ from . import binding
 
 ROW_CANDIDATES = (4, 8, 12, 16)
 GRID_CANDIDATES = (0, 1, 2, 4)
+LANES_CANDIDATES = (0, 32, 64, 96, 128, 192, 256)
 
 
 def size_bucket(n: int) -> int:
@@ -73,8 +78,10 @@ def _time_call(fn, reps: int) -> float:
 
 def autotune(theta, vd, offsets, frame_offsets, seeds, n_hyp: int, tau: float, *,
              offsets_host=None, reps: int = 3, rows=ROW_CANDIDATES, grids=GRID_CANDIDATES,
-             min_gain: float = 0.01, log=None) -> tuple[binding.RVTuning, dict]:
-    """Pick rows_max per bucket and blocks_per_cu for this batch; returns (tuning, report)."""
+             lanes=LANES_CANDIDATES, min_gain: float = 0.01,
+             log=None) -> tuple[binding.RVTuning, dict]:
+    """Pick lanes_max_points, rows_max per bucket and blocks_per_cu for this
+    batch; returns (tuning, report)."""
     n_frames = int(frame_offsets.numel()) - 1
     out = binding.allocate_batch_outputs(n_frames, int(offsets.numel()) - 1, int(theta.numel()),
                                          n_hyp, theta.device)
@@ -88,6 +95,17 @@ def autotune(theta, vd, offsets, frame_offsets, seeds, n_hyp: int, tau: float, *
 
     best_ms = _time_call(lambda: run(best), reps)
     trials = [{"tuning": best.to_dict(), "ms": best_ms}]
+    for m in lanes:
+        if m == best.lanes_max_points:
+            continue
+        cand = binding.RVTuning.from_dict(best.to_dict())
+        cand.lanes_max_points = m
+        ms = _time_call(lambda: run(cand), reps)
+        trials.append({"tuning": cand.to_dict(), "ms": ms})
+        if log:
+            log(f"lanes_max_points {m}: {ms:.3f} ms (best {best_ms:.3f})")
+        if ms < best_ms:
+            best, best_ms = cand, ms
     for b in buckets_in_use(offsets_host):
         for r in rows:
             if r == best.rows_max[b]:

@@ -179,11 +179,17 @@ def test_batch_host_argument_checks(lib):
     bad = binding.RVTuning.from_dict({"rows_max": [16] * 8, "blocks_per_cu": 0, "fp16_min_points": -1})
     assert call(tuning=bad, ws=fake, ws_bytes=1 << 30) == -1
     assert "fp16_min_points" in lib.rv_last_error().decode()
-    # the default tuning: 16 rows everywhere, grid as large as fits, no FP16 form
+    for lanes in (-1, 257):
+        bad = binding.RVTuning.from_dict({"rows_max": [16] * 8, "lanes_max_points": lanes})
+        assert call(tuning=bad, ws=fake, ws_bytes=1 << 30) == -1
+        assert "lanes_max_points" in lib.rv_last_error().decode()
+    # the default tuning: 16 rows everywhere, grid as large as fits, no FP16 form,
+    # lanes = hypotheses up to 64 points
     d = binding.rv_tuning_default()
     assert list(d.rows_max) == [16] * 8 and d.blocks_per_cu == 0 and d.fp16_min_points == 0
+    assert d.lanes_max_points == 64
     assert binding.RVTuning.from_dict(d.to_dict()).to_dict() == d.to_dict()
-    assert ctypes.sizeof(binding.RVTuning) == 4 * (8 + 2)
+    assert ctypes.sizeof(binding.RVTuning) == 4 * (8 + 3)
     # nothing to do
     assert call(K=0, N=0, ws=fake, ws_bytes=1 << 20) == 0
     assert lib.rv_graph_launch(None, None) == -1
@@ -212,7 +218,8 @@ def test_server_host_checks(lib):
                                ("max_batch_frames", 0, "max_batch_frames"),
                                ("n_streams", 9, "n_streams"),
                                ("max_waiting_frames", 0, "max_waiting_frames"),
-                               ("tuning.fp16_min_points", -5, "fp16_min_points")):
+                               ("tuning.fp16_min_points", -5, "fp16_min_points"),
+                               ("tuning.lanes_max_points", 300, "lanes_max_points")):
         c = binding.rv_server_config_default()
         if field.startswith("tuning."):
             setattr(c.tuning, field.split(".")[1], value)

@@ -3,8 +3,10 @@
 * every cluster's outputs are bitwise those of a single-frame call on its frame
   (with that frame's seed), including per-hypothesis counts and inlier bits;
 * parity with the oracle per frame (tests/parity.py protocol);
-* tuning (register rows per size bucket, persistent grid size) never changes a
-  result bit;
+* tuning (register rows per size bucket, persistent grid size, the size up to
+  which clusters score with lanes = hypotheses) never changes a result bit; the
+  lanes = hypotheses form equals the rows form on every cluster size it takes,
+  edge clusters and hypothesis counts included;
 * a captured HIP graph replayed several times, with eager work and
   synchronisations between replays and new input contents, matches the eager
   call every time;
@@ -106,11 +108,50 @@ def test_batch_parity_with_oracle(rv, oracle_mod):
 def test_tuning_never_changes_results(rv):
     batch, H, tau = synth.make_batch_workload("batched", n_frames=4)
     base = _run_batch(rv, batch, H, tau, "tune-default")
-    for rows, per_cu in (([1] * 8, 1), ([4, 4, 8, 8, 12, 12, 16, 16], 3), ([16, 2, 3, 5, 7, 9, 11, 13], 0)):
-        t = rv.RVTuning.from_dict({"rows_max": rows, "blocks_per_cu": per_cu})
-        g = _run_batch(rv, batch, H, tau, f"tune-{per_cu}", tuning=t)
+    for rows, per_cu, lanes in (([1] * 8, 1, 0), ([4, 4, 8, 8, 12, 12, 16, 16], 3, 256),
+                                ([16, 2, 3, 5, 7, 9, 11, 13], 0, 130)):
+        t = rv.RVTuning.from_dict({"rows_max": rows, "blocks_per_cu": per_cu,
+                                   "lanes_max_points": lanes})
+        g = _run_batch(rv, batch, H, tau, f"tune-{per_cu}-{lanes}", tuning=t)
         for k in KEYS + ("hyp_counts", "inlier_bits"):
             assert np.array_equal(g[k], base[k], equal_nan=k in ("vx", "vy", "heading")), k
+
+
+@pytest.mark.parametrize("H", [1, 64, 300, 512])
+def test_lanes_form_equals_rows_form(rv, H):
+    # Clusters of 2..300 points (every size up to the LDS tile of 256 and past
+    # it), with outliers, non-finite points, equal azimuths and two-point
+    # clusters, scored with lanes = hypotheses up to 256 points against the
+    # rows form everywhere: every output and every hypothesis count bitwise.
+    rng = np.random.default_rng(300 + H)
+    clusters = []
+    for n in list(range(2, 70)) + [95, 127, 128, 129, 200, 255, 256, 257, 300]:
+        vx, vy = rng.uniform(-30, 30, 2)
+        th = np.deg2rad(rng.uniform(-60, 60, n)).astype(np.float32)
+        v = vx * np.cos(th.astype(np.float64)) + vy * np.sin(th.astype(np.float64))
+        v = v + rng.normal(0, 0.05, n)
+        out = rng.random(n) < 0.25
+        v[out] = rng.uniform(-40, 40, out.sum())
+        clusters.append((th, v.astype(np.float32)))
+    th, v = clusters[10]
+    th[3], v[5] = np.nan, np.inf
+    clusters.append((np.full(20, 0.3, np.float32), rng.uniform(-2, 2, 20).astype(np.float32)))
+    theta = np.concatenate([c[0] for c in clusters])
+    vd = np.concatenate([c[1] for c in clusters])
+    off = np.zeros(len(clusters) + 1, np.int32)
+    off[1:] = np.cumsum([len(c[0]) for c in clusters])
+    half = len(clusters) // 2
+    frame = synth.Frame(theta=theta, vd=vd, offsets=off, truth_vx=np.zeros(len(clusters)),
+                        truth_vy=np.zeros(len(clusters)), kind=np.zeros(len(theta), np.int8))
+    batch = synth.Batch(frame=frame, frame_offsets=np.array([0, half, len(clusters)], np.int32),
+                        seeds=np.array([0x1A2B, 0x3C4D5E6F7], np.uint64))
+    rows = rv.RVTuning.from_dict({"rows_max": [16] * 8, "lanes_max_points": 0})
+    lanes = rv.RVTuning.from_dict({"rows_max": [16] * 8, "lanes_max_points": 256})
+    a = _run_batch(rv, batch, H, 0.15, f"rows-H{H}", tuning=rows)
+    b = _run_batch(rv, batch, H, 0.15, f"lanes-H{H}", tuning=lanes)
+    for k in KEYS + ("hyp_counts", "inlier_bits"):
+        assert np.array_equal(a[k], b[k], equal_nan=k in ("vx", "vy", "heading")), k
+    assert int((a["status"] == 0).sum()) > len(clusters) // 2
 
 
 def test_graph_replays_match_eager(rv):

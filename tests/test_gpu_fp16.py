@@ -43,6 +43,7 @@ def rv():
 def _run(rv, frame, frame_offsets, seeds, H, tau, fp16_min, label):
     t = rv.rv_tuning_default()
     t.fp16_min_points = fp16_min
+    t.lanes_max_points = 0  # small clusters too take the FP16 form (lanes would take precedence)
     print(f"[gpu] batch fp16_min={fp16_min} {label} K={frame.n_clusters} N={frame.n_points} H={H}",
           flush=True)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
@@ -194,6 +195,7 @@ def test_fp16_form_in_a_captured_graph(rv):
     K, N, F = f.n_clusters, f.n_points, batch.n_frames
     t16 = rv.rv_tuning_default()
     t16.fp16_min_points = 64
+    t16.lanes_max_points = 0
     eager = rv.allocate_batch_outputs(F, K, N, H, "cuda:0", want_bits=True, debug=True)
     replay = rv.allocate_batch_outputs(F, K, N, H, "cuda:0", want_bits=True, debug=True)
     print(f"[gpu] rv_graph_capture_batch fp16_min=64 F={F} K={K} N={N} H={H}", flush=True)

@@ -81,7 +81,7 @@ def test_results_same_alone_and_in_the_mix(rv, oracle_mod):
         if f.n_clusters == 0:
             assert got[j]["vx"].size == 0
             continue
-        alone = parity.run_gpu(f.theta, f.vd, f.offsets, H, tau, seed, debug=False, bits=True,
+        alone = parity.run_gpu(f.theta, f.vd, f.offsets, H, tau, seed, debug=True, bits=True,
                                label=f"alone job{j}")
         for k in KEYS:
             assert np.array_equal(got[j][k], alone[k], equal_nan=k in ("vx", "vy", "heading")), (j, k)
