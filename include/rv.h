@@ -118,6 +118,36 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
                          size_t workspace_bytes, void *stream);
 
 /*
+ * ---- Allocation-free form ----------------------------------------------------
+ *
+ * For callers that cannot allocate device memory around the estimate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  rv_estimate_velocity_noalloc takes the arguments of
+ * rv_estimate_velocity without the workspace and gives the same results bit
+ * for bit (same kernels).  Its workspace is a device array of
+ * RV_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from the first
+ * such call on that GPU until the process ends; the call itself allocates and
+ * frees nothing and records no stage-timing events.  The caller still owns
+ * every input and output.
+ *   - A frame whose rv_workspace_bytes() exceeds RV_NOALLOC_SCRATCH_BYTES is
+ *     rejected with RV_ERR_WORKSPACE before anything is enqueued (96 MiB: up to
+ *     about 3.5 million points).
+ *   - `stream` must belong to the current device (else RV_ERR_INVALID_ARG).
+ *   - All calls on one GPU share its array: calls whose work may overlap on
+ *     that GPU (different streams, or different threads without ordering) race
+ *     and give undefined results.  Calls ordered on one stream are safe; each
+ *     call overwrites what the previous one left there.
+ */
+#define RV_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+
+int rv_estimate_velocity_noalloc(const float *theta, const float *vd,
+                                 const int32_t *cluster_offsets, int64_t n_clusters,
+                                 int64_t n_points, int32_t n_hyp, float tau, uint64_t seed,
+                                 float *vx, float *vy, float *heading, int32_t *n_inliers,
+                                 uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                                 int32_t *hyp_counts, int32_t *best_hyp, void *stream);
+
+/*
  * ---- Many frames at once ---------------------------------------------------
  *
  * The frames share one CSR: frame f owns clusters [frame_offsets[f],

@@ -32,6 +32,7 @@ RV_PAPER_MAX_POINTS = 4096
 RV_MIN_SEED_SEPARATION = 1e-3
 RV_NEAR_TAU_WINDOW = 1e-5
 RV_MAX_HYP = 1 << 20
+RV_NOALLOC_SCRATCH_BYTES = 96 << 20
 
 RV_TUNE_BUCKETS = 8
 
@@ -118,6 +119,11 @@ def load_library() -> ctypes.CDLL:
     lib.rv_estimate_velocity.argtypes = [
         P, P, P, i64, i64, i32, ctypes.c_float, ctypes.c_uint64,
         P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P,
+    ]
+    lib.rv_estimate_velocity_noalloc.restype = ctypes.c_int
+    lib.rv_estimate_velocity_noalloc.argtypes = [
+        P, P, P, i64, i64, i32, ctypes.c_float, ctypes.c_uint64,
+        P, P, P, P, P, P, P, P, P, P,
     ]
     lib.rv_last_error.restype = ctypes.c_char_p
     lib.rv_last_error.argtypes = []
@@ -293,6 +299,36 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     _check(code)
     if owned:
         _used_on(stream, out.values())
+    return {k: v for k, v in out.items() if k != "workspace"}
+
+
+def rv_estimate_velocity_noalloc(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
+                                 n_hyp: int, tau: float, seed: int, out: dict,
+                                 stream: torch.cuda.Stream | None = None) -> dict:
+    """rv_estimate_velocity on the library's own device scratch: no workspace,
+    and the caller's ``out`` (tensors as ``allocate_outputs`` makes them; a
+    ``workspace`` entry is ignored) receives the results.  Frames needing more
+    than RV_NOALLOC_SCRATCH_BYTES of workspace raise RVError; calls that share a
+    GPU must not overlap (they share its scratch)."""
+    lib = load_library()
+    device = theta.device
+    if device.type != "cuda":
+        raise ValueError("theta must be a GPU tensor")
+    n_points = int(theta.numel())
+    n_clusters = int(offsets.numel()) - 1
+    if n_clusters < 0:
+        raise ValueError("offsets needs n_clusters + 1 entries")
+    if int(vd.numel()) != n_points:
+        raise ValueError("theta and vd differ in length")
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    _check(lib.rv_estimate_velocity_noalloc(
+        _dev_ptr(theta, torch.float32, device, "theta"),
+        _dev_ptr(vd, torch.float32, device, "vd"),
+        _dev_ptr(offsets, torch.int32, device, "offsets"),
+        n_clusters, n_points, int(n_hyp), float(tau), int(seed) & 0xFFFFFFFFFFFFFFFF,
+        *_output_ptrs(out, device, n_clusters, n_points, n_hyp),
+        ctypes.c_void_p(stream.cuda_stream)))
     return {k: v for k, v in out.items() if k != "workspace"}
 
 

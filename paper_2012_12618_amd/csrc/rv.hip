@@ -1674,24 +1674,15 @@ BatchArgs make_batch_args(const float *theta, const float *vd, const int32_t *cl
     return a;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t rv_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t n_hyp) {
-    if (n_clusters < 0 || n_points < 0 || n_hyp < 0) return 0;
-    return make_layout(n_clusters, n_points).total;
-}
-
-const char *rv_last_error(void) { return g_error; }
-
-int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *cluster_offsets,
-                         int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau,
-                         uint64_t seed, float *vx, float *vy, float *heading, int32_t *n_inliers,
-                         uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
-                         int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
-                         size_t workspace_bytes, void *stream) {
-    g_error[0] = '\0';
+// rv_estimate_velocity's checks and launches; allow_timing: record stage events
+// when rv_stage_timing is on (the allocation-free entry point never does, since
+// a first event set is created on demand).
+int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                   int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau, uint64_t seed,
+                   float *vx, float *vy, float *heading, int32_t *n_inliers, uint8_t *status,
+                   int32_t *n_near_tau, uint32_t *inlier_bits, int32_t *hyp_counts,
+                   int32_t *best_hyp, void *workspace, size_t workspace_bytes, void *stream,
+                   bool allow_timing) {
     if (n_clusters < 0) return fail(RV_ERR_INVALID_ARG, "n_clusters < 0");
     if (n_points < 0 || n_points > INT32_MAX)
         return fail(RV_ERR_INVALID_ARG, "n_points must be in [0, 2^31 - 1]");
@@ -1746,7 +1737,7 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     o.bits = inlier_bits;
 
     TimedCall tc;
-    const bool timed = take_timed_call(tc);
+    const bool timed = allow_timing && take_timed_call(tc);
     if (timed) (void)hipEventRecord(tc.ev[0], st);
     if (use_small_frame_path(n_clusters, n_points, n_hyp, inlier_bits)) {
         // One launch; its time counts as the scoring stage.
@@ -1785,6 +1776,96 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(RV_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     return RV_OK;
+}
+
+// ---- Allocation-free single-frame entry point ------------------------------
+//
+// rv_estimate_velocity_noalloc keeps its workspace in `scratch`, a device array
+// of RV_NOALLOC_SCRATCH_BYTES that each GPU holds from the first such call on it
+// until the process ends.  In host code the array's name denotes a host-side
+// stand-in, not device memory: host code only passes on the address that
+// hipGetSymbolAddress returns for the current device, looked up once per device
+// and kept in g_scratch.  Every kernel writes the parts of the workspace it
+// reads before reading them (staged points, dispatch order, best keys), so the
+// contents a previous call left need no clearing.
+static __device__ __align__(256) unsigned char scratch[RV_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch[kMaxDevices];
+
+// Device address of `scratch` on the device of `stream` (which must be the
+// current device: the symbol is looked up with that device current).
+int device_scratch(hipStream_t stream, void **ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(RV_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (stream != nullptr) {
+        int sdev = -1;
+        e = hipStreamGetDevice(stream, &sdev);
+        if (e != hipSuccess)
+            return fail(RV_ERR_HIP, "hipStreamGetDevice failed: %s", hipGetErrorString(e));
+        if (sdev != dev)
+            return fail(RV_ERR_INVALID_ARG,
+                        "stream belongs to device %d, the current device is %d", sdev, dev);
+    }
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(RV_ERR_HIP, "device index %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(RV_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s",
+                        hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *ptr = g_scratch[dev];
+    return RV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rv_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t n_hyp) {
+    if (n_clusters < 0 || n_points < 0 || n_hyp < 0) return 0;
+    return make_layout(n_clusters, n_points).total;
+}
+
+const char *rv_last_error(void) { return g_error; }
+
+int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                         int64_t n_clusters, int64_t n_points, int32_t n_hyp, float tau,
+                         uint64_t seed, float *vx, float *vy, float *heading, int32_t *n_inliers,
+                         uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                         int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                         size_t workspace_bytes, void *stream) {
+    g_error[0] = '\0';
+    return estimate_frame(theta, vd, cluster_offsets, n_clusters, n_points, n_hyp, tau, seed, vx,
+                          vy, heading, n_inliers, status, n_near_tau, inlier_bits, hyp_counts,
+                          best_hyp, workspace, workspace_bytes, stream, true);
+}
+
+int rv_estimate_velocity_noalloc(const float *theta, const float *vd,
+                                 const int32_t *cluster_offsets, int64_t n_clusters,
+                                 int64_t n_points, int32_t n_hyp, float tau, uint64_t seed,
+                                 float *vx, float *vy, float *heading, int32_t *n_inliers,
+                                 uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                                 int32_t *hyp_counts, int32_t *best_hyp, void *stream) {
+    g_error[0] = '\0';
+    const size_t need = rv_workspace_bytes(n_clusters, n_points, n_hyp);
+    if (need > RV_NOALLOC_SCRATCH_BYTES)
+        return fail(RV_ERR_WORKSPACE,
+                    "frame of %lld clusters and %lld points needs %zu bytes of workspace; the "
+                    "allocation-free entry point holds %zu",
+                    (long long)n_clusters, (long long)n_points, need,
+                    (size_t)RV_NOALLOC_SCRATCH_BYTES);
+    void *ws = nullptr;
+    if (int rc = device_scratch((hipStream_t)stream, &ws)) return rc;
+    return estimate_frame(theta, vd, cluster_offsets, n_clusters, n_points, n_hyp, tau, seed, vx,
+                          vy, heading, n_inliers, status, n_near_tau, inlier_bits, hyp_counts,
+                          best_hyp, ws, RV_NOALLOC_SCRATCH_BYTES, stream, false);
 }
 
 int rv_stage_timing(int enable) {

@@ -49,6 +49,24 @@ def test_header_constants_match_binding():
     assert "RV_NEAR_TAU_WINDOW 1e-5" in text and binding.RV_NEAR_TAU_WINDOW == 1e-5
 
 
+def test_noalloc_scratch_limit(lib):
+    # The allocation-free entry point refuses a frame whose workspace exceeds
+    # its device scratch before any HIP call (fake pointers: never used).
+    from paper_2012_12618_amd import binding
+
+    text = open(HEADER).read()
+    assert "RV_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)" in text
+    assert binding.RV_NOALLOC_SCRATCH_BYTES == 96 << 20
+    fake = ctypes.c_void_p(4096)
+    n = 3_600_000
+    assert binding.rv_workspace_bytes(1, n, 64) > binding.RV_NOALLOC_SCRATCH_BYTES
+    assert binding.rv_workspace_bytes(4096, 2_723_399, 1024) <= binding.RV_NOALLOC_SCRATCH_BYTES
+    rc = lib.rv_estimate_velocity_noalloc(fake, fake, fake, 1, n, 64, 0.15, 1, fake, fake, fake,
+                                          fake, fake, None, None, None, None, None)
+    assert rc == -2
+    assert "allocation-free" in lib.rv_last_error().decode()
+
+
 def test_workspace_bytes(lib):
     from paper_2012_12618_amd import binding
 
