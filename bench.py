@@ -744,6 +744,8 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
         "host": host_cpus()}
 
     f16, f32 = forms["fp16"], forms["fp32"]
+    recount = fp16_recount_stats(f16["res"]["hyp_counts"], f32["res"]["hyp_counts"],
+                                 np.diff(frame.offsets), n_hyp)
     score16 = f16["stage_ms"]["score"]
     achieved = FLOP_PER_EVAL * evals / (score16 / 1e3) / 1e12
     sec = f16["ms_per_step"] / 1e3
@@ -768,6 +770,7 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
                       "stage_ms": f32["stage_ms"]},
         "fp16_over_fp32_time": f16["ms_per_step"] / f32["ms_per_step"],
         "outputs_bitwise_equal_to_fp32_form": identical,
+        "fp16_recount": recount,
         "oracle_error": dict(err, scope="FP16-form results (bitwise the float32 form's) against "
                                          "the FP64 oracle, per cluster"),
         "stage_ms": f16["stage_ms"],
@@ -781,6 +784,54 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
     }
     print(json.dumps(line), flush=True)
     return 0 if identical else 1
+
+
+def fp16_recount_stats(hi, exact, sizes, n_hyp, block=256):
+    """Work of the FP16 form's exact re-count, per scoring block of 256
+    hypotheses, from the per-hypothesis counts of the two forms: hi (FP16 form,
+    an upper bound of the float32 count) and exact (float32 form).  A block
+    counts exactly, in its first pass, the hypothesis with the largest (hi,
+    lowest index) among those with a finite widened threshold together with
+    those without one ("wide": their FP16 row counted every finite point, seen
+    here as hi equal to the cluster size with a smaller exact count); then
+    every other hypothesis with hi at least the first one's exact count, 64 per
+    pass.  Hypotheses with hi = 0 (invalid, or no point within the widened
+    threshold) are never candidates."""
+    import numpy as np
+
+    sizes = np.asarray(sizes, np.int64)
+    n_clusters = sizes.size
+    hi = np.asarray(hi, np.int64).reshape(n_clusters, n_hyp)
+    ex = np.asarray(exact, np.int64).reshape(n_clusters, n_hyp)
+    rows = np.arange(n_clusters)
+    cands, wides, slack = [], [], []
+    for b0 in range(0, n_hyp, block):
+        h = hi[:, b0:b0 + block]
+        e = ex[:, b0:b0 + block]
+        wide = (h >= sizes[:, None]) & (e < h)
+        finite = (h > 0) & ~wide
+        top = np.argmax(np.where(finite, h, -1), axis=1)  # first maximum: the lowest index
+        has_top = finite[rows, top]
+        t = np.where(has_top, e[rows, top], 0)
+        c = finite & (h >= t[:, None])
+        c[rows, top] &= ~has_top
+        cands.append(c.sum(axis=1))
+        wides.append(wide.sum(axis=1))
+        slack.append(h - e)
+    cands = np.concatenate(cands)
+    wides = np.concatenate(wides)
+    slack = np.concatenate(slack, axis=1)
+    passes = 1 + (cands + 63) // 64
+    return {"blocks": int(cands.size),
+            "wide_per_block": {"mean": float(wides.mean()), "max": int(wides.max())},
+            "candidates_per_block": {"mean": float(cands.mean()), "p50": float(np.median(cands)),
+                                     "p99": float(np.quantile(cands, 0.99)), "max": int(cands.max())},
+            "exact_passes_per_block": {"mean": float(passes.mean()), "max": int(passes.max())},
+            "hi_minus_exact": {"mean": float(slack.mean()), "max": int(slack.max()),
+                               "min": int(slack.min())},
+            "scope": "per block of 256 hypotheses: hypotheses without a finite FP16 threshold, "
+                     "candidates re-counted in float32 after the first exact pass, and exact "
+                     "passes over the cluster (the first, then 64 candidates per pass)"}
 
 
 def host_comparators(f, H):

@@ -488,23 +488,55 @@ __device__ __forceinline__ float2 fp16_hypothesis(float hx, float hy, float rx, 
     return make_float2(__builtin_bit_cast(float, nd), tau + band);
 }
 
+// One hypothesis (nd = half2 -(h - r), threshold t) against four rows of
+// points in the FP16 form: e = v_dot2_f32_f16(cs, nd) + w, each product in
+// FP16 and the sum in float32, then |e| < t as four 64-lane masks; returns the
+// number of set bits.  The VOP3P v_dot2_f32_f16 writes its own destination:
+// the compiler's choice, the accumulating v_dot2c_f32_f16, overwrites w and so
+// needs a copy of w for every row and hypothesis (three vector instructions
+// per row instead of two).  One asm block, so that each compare issues three
+// instructions after the dot product whose result it reads: gfx950 needs three
+// wait states between a DOT instruction's write and another VALU instruction's
+// read of that register.  Every lane must be active (the masks are ballots).
+__device__ __forceinline__ uint32_t fp16_count4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                float w0, float w1, float w2, float w3,
+                                                uint32_t nd, float t) {
+    float e0, e1, e2, e3;
+    uint64_t m0, m1, m2, m3;
+    asm("v_dot2_f32_f16 %0, %8, %12, %14\n\t"
+        "v_dot2_f32_f16 %1, %9, %12, %15\n\t"
+        "v_dot2_f32_f16 %2, %10, %12, %16\n\t"
+        "v_dot2_f32_f16 %3, %11, %12, %17\n\t"
+        "v_cmp_lt_f32_e64 %4, |%0|, %13\n\t"
+        "v_cmp_lt_f32_e64 %5, |%1|, %13\n\t"
+        "v_cmp_lt_f32_e64 %6, |%2|, %13\n\t"
+        "v_cmp_lt_f32_e64 %7, |%3|, %13"
+        : "=&v"(e0), "=&v"(e1), "=&v"(e2), "=&v"(e3), "=s"(m0), "=s"(m1), "=s"(m2), "=s"(m3)
+        : "v"(c0), "v"(c1), "v"(c2), "v"(c3), "v"(nd), "v"(t), "v"(w0), "v"(w1), "v"(w2),
+          "v"(w3));
+    return (uint32_t)(__builtin_popcountll(m0) + __builtin_popcountll(m1) +
+                      __builtin_popcountll(m2) + __builtin_popcountll(m3));
+}
+
 // score_rows in the FP16 form: returns hi of hypothesis q of the wave in lane q.
+// R is a multiple of four; rows past the points are padding (w = +inf).
 template <int R>
 __device__ __forceinline__ uint32_t score_rows_fp16(const float2 *__restrict__ cs_chunk,
                                                     const float *__restrict__ v_chunk, int npts,
                                                     int lane, const float4 *hp, int ng, float rx,
                                                     float ry) {
-    half2_t cs[R];
+    static_assert(R % 4 == 0, "rows come in blocks of four");
+    uint32_t cs[R];
     float w[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int len = npts - r * kWave;
-        cs[r] = half2_t{(_Float16)0.0f, (_Float16)0.0f};
+        cs[r] = 0u;
         w[r] = __builtin_inff();
         if (lane < len) {
             const float2 q = cs_chunk[r * kWave + lane];
             const float v = v_chunk[r * kWave + lane];
-            cs[r] = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(q.x, q.y));
+            cs[r] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(q.x, q.y));
             w[r] = __builtin_fmaf(-ry, q.y, __builtin_fmaf(-rx, q.x, v));
         }
     }
@@ -515,14 +547,12 @@ __device__ __forceinline__ uint32_t score_rows_fp16(const float2 *__restrict__ c
         const float ht[kHypGroup] = {h0.y, h0.w, h1.y, h1.w};
 #pragma unroll
         for (int u = 0; u < kHypGroup; ++u) {
-            const half2_t nd = __builtin_bit_cast(half2_t, hd[u]);
+            const uint32_t nd = __builtin_bit_cast(uint32_t, hd[u]);
             uint32_t n = 0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const float e = __builtin_amdgcn_fdot2(cs[r], nd, w[r], false);
-                n += (uint32_t)__builtin_popcountll(
-                    __builtin_amdgcn_ballot_w64(__builtin_fabsf(e) < ht[u]));
-            }
+            for (int r = 0; r < R; r += 4)
+                n += fp16_count4(cs[r], cs[r + 1], cs[r + 2], cs[r + 3], w[r], w[r + 1], w[r + 2],
+                                 w[r + 3], nd, ht[u]);
             counts = (uint32_t)amdgcn_writelane((int)n, g * kHypGroup + u, (int)counts);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -530,7 +560,8 @@ __device__ __forceinline__ uint32_t score_rows_fp16(const float2 *__restrict__ c
     return counts;
 }
 
-// score_cluster in the FP16 form.
+// score_cluster in the FP16 form (a pass's rows rounded up to a multiple of
+// four).
 __device__ __forceinline__ uint32_t score_cluster_fp16(const Points &pts, Span sp, int lane,
                                                        const float4 *hp, int nh, int rows_max,
                                                        float rx, float ry) {
@@ -541,17 +572,15 @@ __device__ __forceinline__ uint32_t score_cluster_fp16(const Points &pts, Span s
     for (int64_t base = sp.lo; base < end; base += pass) {
         const int64_t left = end - base;
         const int npts = (int)(left < pass ? left : pass);
-        const int rows = (npts + kWave - 1) / kWave;
+        const int blocks = (npts + 4 * kWave - 1) / (4 * kWave);
         const float2 *cs_chunk = pts.cs32 + base;
         const float *v_chunk = pts.v32 + base;
-        switch (rows) {
-#define RV_ROWS16(R)                                                                       \
-    case R:                                                                                \
-        total += score_rows_fp16<R>(cs_chunk, v_chunk, npts, lane, hp, ng, rx, ry);        \
+        switch (blocks) {
+#define RV_ROWS16(B)                                                                       \
+    case B:                                                                                \
+        total += score_rows_fp16<4 * B>(cs_chunk, v_chunk, npts, lane, hp, ng, rx, ry);    \
         break;
-            RV_ROWS16(1) RV_ROWS16(2) RV_ROWS16(3) RV_ROWS16(4) RV_ROWS16(5) RV_ROWS16(6)
-            RV_ROWS16(7) RV_ROWS16(8) RV_ROWS16(9) RV_ROWS16(10) RV_ROWS16(11) RV_ROWS16(12)
-            RV_ROWS16(13) RV_ROWS16(14) RV_ROWS16(15) RV_ROWS16(16)
+            RV_ROWS16(1) RV_ROWS16(2) RV_ROWS16(3) RV_ROWS16(4)
 #undef RV_ROWS16
             default: break;
         }
@@ -740,24 +769,59 @@ __device__ __forceinline__ void score_block_fp16(Span sp, ClusterId id, int b, i
     uint32_t hi = 0;
     if (nh > 0) hi = score_cluster_fp16(pts, sp, lane, sh.h16 + wave * (kWave / 2), nh, rows_max, rx, ry);
     const bool valid = lane < nh && !__builtin_isnan(h32[tid].x);
+    // A hypothesis without a finite widened threshold (offset beyond the FP16
+    // range) counted every finite point: its hi says nothing about its count.
+    const bool wide = valid && !(reinterpret_cast<const float2 *>(sh.h16)[tid].y < __builtin_inff());
     if (hyp_counts != nullptr && lane < nh) hyp_counts[id.out * n_hyp + base + tid] = (int32_t)hi;
-    key = valid ? hyp_key(hi, base + tid) : 0ull;
+    key = valid && !wide ? hyp_key(hi, base + tid) : 0ull;
     key = wave_max_u64(key);
-    if (lane == 0) sh.key[wave] = key;
+    const uint64_t wide_mask = __builtin_amdgcn_ballot_w64(wide);
+    if (lane == 0) {
+        sh.key[wave] = key;
+        sh.n_cand[wave] = (uint32_t)__builtin_popcountll(wide_mask);
+    }
     __syncthreads();
     unsigned long long top = 0;
+    uint32_t wide_before = 0, n_wide = 0;
 #pragma unroll
-    for (int w = 0; w < kScoreBlock / kWave; ++w) top = sh.key[w] > top ? sh.key[w] : top;
+    for (int w = 0; w < kScoreBlock / kWave; ++w) {
+        top = sh.key[w] > top ? sh.key[w] : top;
+        const uint32_t c = sh.n_cand[w];
+        wide_before += w < wave ? c : 0u;
+        n_wide += c;
+    }
     top = uniform_u64(top);
-    if (top == 0) return;  // no valid hypothesis in this block
+    n_wide = __builtin_amdgcn_readfirstlane(n_wide);
+    if (top == 0 && n_wide == 0) return;  // no valid hypothesis in this block
 
-    // 4. Exact count of the top hypothesis, then of every candidate.
+    // 4. Exact float32 counts.  First pass: the hypothesis with the largest
+    // (hi, lowest index) among those with a finite threshold (T = its exact
+    // count) together with the hypotheses without one, up to 64 in all.  Then
+    // every other valid hypothesis with hi >= T, 64 per pass.  A hypothesis
+    // left out has n_h <= hi_h < T, so the best exact key is the float32 form's.
+    const uint32_t has_top = top != 0 ? 1u : 0u;
     const uint32_t h_top = 0xFFFFFFFFu - (uint32_t)top;
-    if (tid == 0) reinterpret_cast<float2 *>(sh.list)[0] = h32[h_top - (uint32_t)base];
+    const uint32_t wide_rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(wide_mask >> 32),
+                                  __builtin_amdgcn_mbcnt_lo((uint32_t)wide_mask, 0u));
+    const uint32_t slot = has_top + wide_before + wide_rank;
+    const bool first = wide && slot < (uint32_t)kWave;  // counted in the first pass
+    if (first) {
+        reinterpret_cast<float2 *>(sh.list)[slot] = h32[tid];
+        sh.idx[slot] = (uint32_t)tid;
+    }
+    if (tid == 0 && has_top) {
+        reinterpret_cast<float2 *>(sh.list)[0] = h32[h_top - (uint32_t)base];
+        sh.idx[0] = h_top - (uint32_t)base;
+    }
     __syncthreads();
-    const uint32_t t_exact = __builtin_amdgcn_readfirstlane(exact_counts(sp, pts, tau, 1, sh, wave, lane));
-    unsigned long long best = hyp_key(t_exact, h_top);
-    const bool cand = valid && (uint32_t)(base + tid) != h_top && hi >= t_exact;
+    const uint32_t n1 = has_top + n_wide < (uint32_t)kWave ? has_top + n_wide : (uint32_t)kWave;
+    const uint32_t c1 = exact_counts(sp, pts, tau, (int)n1, sh, wave, lane);
+    const uint32_t t_exact = has_top ? __builtin_amdgcn_readfirstlane(c1) : 0u;
+    unsigned long long best = lane < (int)n1 ? hyp_key(c1, base + sh.idx[lane]) : 0ull;
+    best = wave_max_u64(best);
+    const bool cand = valid && !first && (!has_top || (uint32_t)(base + tid) != h_top) &&
+                      hi >= t_exact;
     const uint64_t m = __builtin_amdgcn_ballot_w64(cand);
     if (lane == 0) sh.n_cand[wave] = (uint32_t)__builtin_popcountll(m);
     __syncthreads();
