@@ -49,6 +49,10 @@ WORKLOAD_TEXT["paper-sweep"] = (
     "paper-literal variant (normalised line fit, MAD threshold, <= test, least-squares refit) "
     "on the shapes of the paper's Tables I and II: {8, 16, 32, 64} clusters x {100, 150} points, "
     "20% uniform outliers, 256 trials per cluster, FP64")
+WORKLOAD_TEXT["issue-rates"] = (
+    "wave64 issue rates of the scoring loops' instructions (v_fma_f32, compares, v_dot2_f32_f16, "
+    "the scalar popcount) and of the float32 and FP16 scoring rows, eight waves per SIMD "
+    "(_lib/issue_probe)")
 FRAME_WORKLOADS = ("dense", "small")
 
 
@@ -1059,6 +1063,24 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
     return out
 
 
+def issue_rates_bench() -> int:
+    """Runs the issue-rate probe built beside the library and prints its JSON."""
+    import subprocess
+
+    probe = os.path.join(ROOT, "paper_2012_12618_amd", "_lib", "issue_probe")
+    if not os.path.exists(probe):
+        print(f"bench.py: {probe} is missing (run __graft_entry__.build())", file=sys.stderr)
+        return 1
+    res = subprocess.run([probe], capture_output=True, text=True, timeout=120)
+    if res.returncode != 0:
+        print(res.stderr, file=sys.stderr)
+        return res.returncode
+    rec = json.loads(res.stdout)
+    rec.update({"metric": "wave64 instruction issue rates", "workload": WORKLOAD_TEXT["issue-rates"]})
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -1109,6 +1131,9 @@ def main() -> int:
     if os.environ.get("WORLD_SIZE", "1") not in ("", "1"):
         print("bench.py: run on a single rank", file=sys.stderr)
         return 2
+
+    if args.workload == "issue-rates":
+        return issue_rates_bench()
 
     import numpy as np
     import torch

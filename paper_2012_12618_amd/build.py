@@ -1,6 +1,8 @@
 """Build the gfx950 shared library ``_lib/librv.so`` from ``csrc/rv.hip`` (kernels
 and estimator entry points), ``csrc/rv_paper.hip`` (paper-literal variant) and
-``csrc/rv_server.cpp`` (frame server).
+``csrc/rv_server.cpp`` (frame server), and the measurement program
+``_lib/issue_probe`` from ``csrc/issue_probe.hip`` (instruction issue rates,
+run by ``bench.py --workload issue-rates``).
 
 Usage: ``python -m paper_2012_12618_amd.build`` (also called by the repository's
 ``__graft_entry__.build()``).  hipcc cross-compiles for gfx950 without a GPU.
@@ -18,6 +20,8 @@ SRCS = [os.path.join(HERE, "csrc", n) for n in ("rv.hip", "rv_paper.hip", "rv_se
 INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "librv.so")
+PROBE_SRC = os.path.join(HERE, "csrc", "issue_probe.hip")
+PROBE = os.path.join(LIB_DIR, "issue_probe")
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -36,10 +40,7 @@ def hipcc_path() -> str:
     return os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
-    os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc_path(), *HIP_FLAGS, *(extra_flags or []), "-I", INCLUDE, "-o", tmp, *SRCS]
+def _hipcc(cmd: list[str], verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -50,7 +51,16 @@ def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs))
+
+
+def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
+    os.makedirs(LIB_DIR, exist_ok=True)
+    tmp = LIB + ".tmp"
+    _hipcc([hipcc_path(), *HIP_FLAGS, *(extra_flags or []), "-I", INCLUDE, "-o", tmp, *SRCS], verbose)
     os.replace(tmp, LIB)
+    probe_flags = [f for f in HIP_FLAGS if f not in ("-fPIC", "-shared")]
+    _hipcc([hipcc_path(), *probe_flags, "-o", PROBE + ".tmp", PROBE_SRC], verbose)
+    os.replace(PROBE + ".tmp", PROBE)
     return LIB
 
 

@@ -15,9 +15,13 @@
 //           registers (rows of 64 points), every lane reads the same hypothesis
 //           from LDS, and per point two float32 FMAs and one compare produce a
 //           64-lane ballot that the scalar unit popcounts (Alg. 1's distance test
-//           and inlier count).  The best (count, lowest index) key of the block
-//           is merged per cluster with a 64-bit atomic maximum (Sec. 3.1: the
-//           trial with the most inliers is kept).
+//           and inlier count).  The last n mod 64 points of a cluster, when
+//           fewer than 32, and whole clusters of at most 64 points are scored
+//           with lanes = hypotheses instead (points broadcast from LDS, each
+//           lane counting its own inliers; same arithmetic, same counts).  The
+//           best (count, lowest index) key of the block is merged per cluster
+//           with a 64-bit atomic maximum (Sec. 3.1: the trial with the most
+//           inliers is kept).
 //   refit   one wave per cluster, or the whole workgroup for clusters of
 //           1024 points or more: FP64 re-classification under the kept
 //           hypothesis, FP64 normal-equation sums in a fixed reduction tree,
@@ -350,6 +354,64 @@ __device__ __forceinline__ uint32_t score_cluster(const Points &pts, Span sp, in
     return total;
 }
 
+// The last t = n mod 64 points of a cluster, when t < kTailLanesMax, are
+// scored with lanes = hypotheses instead of as one partly idle row: a row
+// costs two FMAs and a compare for 64 lanes whatever t is, while each tail
+// point costs every lane two FMAs, a compare and an add (about 12 SIMD-cycles
+// per point against about 10 per row and hypothesis), so below about 50 points
+// the tail is cheaper this way (thresholds of 32, 48 and 63 measured alike:
+// about 5 % off the small frame, 1 % off the batched step, no change on the
+// dense frame).  Thread tid holds hypothesis tid of the block
+// in both forms, so the two partial counts add up in the same thread; the
+// residual and the test are the rows form's, so every count is the same bit
+// for bit.
+constexpr int kTailLanesMax = 32;
+
+struct TailShared {
+    float4 c[kWave / 4], s[kWave / 4], v[kWave / 4];  // padded with (0, 0, +inf)
+};
+
+__device__ __forceinline__ int lanes_tail(int64_t n) {
+    const int t = (int)(n % kWave);
+    return t < kTailLanesMax ? t : 0;
+}
+
+// Stages the tail points of sp (tail of them, block-uniform) into LDS; the
+// caller's next block barrier publishes them.
+__device__ __forceinline__ void stage_tail(const Points &pts, Span sp, int tail, TailShared &sh) {
+    const int tid = threadIdx.x;
+    if (tid < ((tail + 3) & ~3)) {
+        float c = 0.0f, sn = 0.0f, v = __builtin_inff();  // a padding point never counts
+        if (tid < tail) {
+            const int64_t p = sp.lo + sp.n - tail + tid;
+            const float2 q = pts.cs32[p];
+            c = q.x;
+            sn = q.y;
+            v = pts.v32[p];
+        }
+        reinterpret_cast<float *>(sh.c)[tid] = c;
+        reinterpret_cast<float *>(sh.s)[tid] = sn;
+        reinterpret_cast<float *>(sh.v)[tid] = v;
+    }
+}
+
+// Inliers of hypothesis (hx, hy) among the staged tail points (LDS broadcasts).
+__device__ __forceinline__ uint32_t tail_count(const TailShared &sh, int tail, float hx, float hy,
+                                               float tau) {
+    uint32_t cnt = 0;
+    for (int q = 0; q < (tail + 3) / 4; ++q) {
+        const float4 c = sh.c[q], sn = sh.s[q], v = sh.v[q];
+        const float cc[4] = {c.x, c.y, c.z, c.w}, ss[4] = {sn.x, sn.y, sn.z, sn.w};
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float e = __builtin_fmaf(-hy, ss[u], __builtin_fmaf(-hx, cc[u], vv[u]));
+            cnt += __builtin_fabsf(e) < tau ? 1u : 0u;
+        }
+    }
+    return cnt;
+}
+
 // A cluster's hypotheses: Philox key and the cluster index of the counter
 // (the cluster's index within its own frame), and the index of its outputs.
 struct ClusterId {
@@ -372,6 +434,7 @@ template <bool kUniformTail>
 __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_t n_hyp,
                                             const Points &pts, float tau, int rows_max,
                                             float4 *s_hyp, unsigned long long *s_key,
+                                            TailShared &s_tail,
                                             unsigned long long *__restrict__ best_key,
                                             int32_t *__restrict__ hyp_counts) {
     const int tid = threadIdx.x;
@@ -380,6 +443,8 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
         if (hyp_counts != nullptr && h < n_hyp) hyp_counts[id.out * n_hyp + h] = 0;
         return;
     }
+    const int tail = lanes_tail(sp.n);  // the same for the whole block
+    if (tail > 0) stage_tail(pts, sp, tail, s_tail);
     {
         float hx = __builtin_nanf(""), hy = __builtin_nanf("");
         if (h < n_hyp) {
@@ -397,14 +462,18 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
     unsigned long long key = 0;
     if (h0 < n_hyp) {
         const int nh = (int64_t)n_hyp - h0 < kWave ? (int)((int64_t)n_hyp - h0) : kWave;
-        const uint32_t cnt =
-            score_cluster(pts, sp, lane, s_hyp + wave * (kWave / 2), nh, tau, rows_max);
+        Span rows = sp;
+        rows.n -= tail;
+        uint32_t cnt =
+            score_cluster(pts, rows, lane, s_hyp + wave * (kWave / 2), nh, tau, rows_max);
         // The lane's own hypothesis is re-read from LDS rather than kept in
         // registers through the scoring loop.
+        const float2 own = reinterpret_cast<const float2 *>(s_hyp)[tid];
+        if (tail > 0) cnt += tail_count(s_tail, tail, own.x, own.y, tau);
         const int64_t hl = h0 + lane;
         if (lane < nh) {
             if (hyp_counts != nullptr) hyp_counts[id.out * n_hyp + hl] = (int32_t)cnt;
-            if (!__builtin_isnan(reinterpret_cast<const float2 *>(s_hyp)[tid].x))
+            if (!__builtin_isnan(own.x))
                 key = ((unsigned long long)cnt << 32) | (0xFFFFFFFFull - (uint32_t)hl);
         }
     }
@@ -620,6 +689,9 @@ __device__ __forceinline__ unsigned long long hyp_key(uint32_t count, int64_t h)
 
 constexpr int kLaneTile = 256;        // points staged in LDS: the largest cluster of this form
 constexpr int kDefaultLanesMax = 64;  // default Tuning::lanes_max
+// Single-frame calls (score_kernel, small_frame_kernel): clusters of at most
+// this many points score with lanes = hypotheses.
+constexpr int kSingleLanesMax = 64;
 
 struct LaneShared {
     float4 c[kLaneTile / 4], s[kLaneTile / 4], v[kLaneTile / 4];  // padded with (0, 0, +inf)
@@ -1097,6 +1169,8 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     int32_t *__restrict__ hyp_counts) {
     __shared__ float4 s_hyp[kScoreBlock / 2];  // (vx, vy) pairs, two per float4
     __shared__ unsigned long long s_key[kScoreBlock / kWave];
+    __shared__ LaneShared s_lanes;
+    __shared__ TailShared s_tail;
     const uint32_t xcd = blockIdx.x % kXcds;
     const uint32_t r = blockIdx.x / kXcds;
     const int64_t j = xcd + (int64_t)kXcds * (r / (uint32_t)blocks_per_cluster);
@@ -1108,8 +1182,13 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     id.local = (uint32_t)k;
     id.key0 = key0;
     id.key1 = key1;
-    score_block<false>(cluster_span(off, k, n_points), id, b, n_hyp, pts, tau, kRowsMax, s_hyp,
-                       s_key, best_key, hyp_counts);
+    const Span sp = cluster_span(off, k, n_points);
+    if (sp.ok && sp.n >= 2 && sp.n <= kSingleLanesMax) {  // the same for the whole block
+        score_block_lanes(sp, id, b, n_hyp, pts, tau, s_lanes, best_key, hyp_counts);
+        return;
+    }
+    score_block<false>(sp, id, b, n_hyp, pts, tau, kRowsMax, s_hyp, s_key, s_tail, best_key,
+                       hyp_counts);
 }
 
 // Refit of a frame's or batch's clusters over their planned (largest-first)
@@ -1194,6 +1273,8 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     __shared__ unsigned long long s_key[kScoreBlock / kWave];
     __shared__ double s_sum[kRefitBlock / kWave][5];
     __shared__ int s_cnt[kRefitBlock / kWave][2];
+    __shared__ LaneShared s_lanes;
+    __shared__ TailShared s_tail;
     const int64_t k = blockIdx.x;
     const Span sp = cluster_span(off, k, n_points);
     for (int64_t p = sp.lo + threadIdx.x; p < sp.lo + sp.n; p += kScoreBlock)
@@ -1205,12 +1286,18 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     id.local = (uint32_t)k;
     id.key0 = key0;
     id.key1 = key1;
-    score_block<false>(sp, id, 0, n_hyp, pts, tau, kRowsMax, s_hyp, s_key, best_key, o.hyp_counts);
     // The workgroup's own block key is the cluster's best (one block per
-    // cluster); the per-wave keys are still in LDS after score_block's barrier.
+    // cluster); the per-wave keys are still in LDS after the scoring's barrier.
+    const bool lanes = sp.ok && sp.n >= 2 && sp.n <= kSingleLanesMax;  // block-uniform
+    if (lanes)
+        score_block_lanes(sp, id, 0, n_hyp, pts, tau, s_lanes, best_key, o.hyp_counts);
+    else
+        score_block<false>(sp, id, 0, n_hyp, pts, tau, kRowsMax, s_hyp, s_key, s_tail,
+                           best_key, o.hyp_counts);
+    const unsigned long long *keys = lanes ? s_lanes.key : s_key;
     unsigned long long best = 0;
 #pragma unroll
-    for (int w = 0; w < kScoreBlock / kWave; ++w) best = s_key[w] > best ? s_key[w] : best;
+    for (int w = 0; w < kScoreBlock / kWave; ++w) best = keys[w] > best ? keys[w] : best;
     refit_block(sp, id, uniform_u64(best), pts, tau, o, s_sum, s_cnt);
 }
 
@@ -1394,6 +1481,7 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(kFp
     __shared__ unsigned long long s_item;
     __shared__ Fp16Shared s_fp16;  // unreferenced, so not allocated, when !kFp16
     __shared__ LaneShared s_lanes;
+    __shared__ TailShared s_tail;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lane = threadIdx.x % kWave;
     const uint32_t home = blockIdx.x % kXcds;
@@ -1428,7 +1516,7 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(kFp
                 }
             }
             score_block<true>(desc_span(d), desc_id(d), b, n_hyp, pts, tau, d.rows, s_hyp, s_key,
-                              best_key, hyp_counts);
+                              s_tail, best_key, hyp_counts);
         }
     }
 }
