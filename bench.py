@@ -449,10 +449,12 @@ def batch_bench(args, torch, binding, synth, dev) -> dict:
     return line
 
 
-def served_bench(args, torch, binding, synth, dev) -> dict:
+def served_bench(args, torch, binding, synth, dev, extra_fp16: int = 0) -> dict:
     """Served form: paced arrivals for latency, then the same frames as fast as
     the server takes them for throughput; the per-frame form (one frame per
-    launch, one slot) on the same traffic for comparison."""
+    launch, one slot) on the same traffic for comparison.  extra_fp16 > 0: the
+    served form also runs in the FP16 residual form for clusters of at least
+    that many points ("served_fp16_form"), against the same per-frame run."""
     from paper_2012_12618_amd import serve
 
     name = args.workload
@@ -468,23 +470,27 @@ def served_bench(args, torch, binding, synth, dev) -> dict:
 
         tuning = tuner.load(args.tuning, torch.cuda.get_device_name(dev), n_hyp)
 
-    def make_server(max_batch, n_streams, fp16):
+    def make_server(max_batch, n_streams, fp16_min):
         cfg = binding.rv_server_config_default()
         cfg.n_hyp, cfg.tau = n_hyp, tau
         cfg.hbm_budget_bytes = 16 << 30
         cfg.max_batch_frames, cfg.n_streams = max_batch, n_streams
         if tuning is not None:
             cfg.tuning = tuning
-        if fp16 and args.fp16_min_points > 0:  # the served form only; the per-frame form stays FP32
-            cfg.tuning.fp16_min_points = args.fp16_min_points
+        if fp16_min > 0:  # served forms only; the per-frame form stays FP32
+            cfg.tuning.fp16_min_points = fp16_min
         return binding.RVServer(cfg)
 
     def seed_of(a):
         return synth.frame_seed(name, a.index)
 
     out = {}
-    for form, (max_batch, n_streams) in (("served", (64, 2)), ("per_frame", (1, 1))):
-        server = make_server(max_batch, n_streams, form == "served")
+    forms = [("served", 64, 2, args.fp16_min_points)]
+    if extra_fp16 > 0:
+        forms.append(("served_fp16", 64, 2, extra_fp16))
+    forms.append(("per_frame", 1, 1, 0))
+    for form, max_batch, n_streams, fp16_min in forms:
+        server = make_server(max_batch, n_streams, fp16_min)
         try:
             print(f"[bench] {form}: warmup", file=sys.stderr, flush=True)
             serve.run_traffic(server, frames, warm, seed_of, n_hyp, paced=False,
@@ -564,6 +570,9 @@ def served_bench(args, torch, binding, synth, dev) -> dict:
                      "kernel_ms": score_ms_total / max(n_calls, 1), "launches": n_calls},
         "cpu_baseline": cpu,
     }
+    if extra_fp16 > 0:
+        paced_h, sat_h, _ = out["served_fp16"]
+        line["served_fp16_form"] = dict(brief(paced_h, sat_h), fp16_min_points=extra_fp16)
     return line
 
 
@@ -1018,8 +1027,10 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
     that one run reports them all: the small frame (the paper's Table I shape:
     per-step time and latency over 1000 distinct frames), the 256-frame batched
     form (one graph replay per step, and the per-frame form on the same
-    frames), and the served form at 64 radars x 20 frames/s (latency and
-    saturated throughput of the served and the per-frame forms)."""
+    frames, in the float32 form and in the FP16 residual form), and the served
+    form at 64 radars x 20 frames/s (latency and saturated throughput of the
+    served and the per-frame forms; the served form in float32, then in the FP16
+    residual form)."""
     import copy
 
     out = {}
@@ -1046,20 +1057,38 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
         "per_frame_form": b["per_frame_form"],
         "batched_over_per_frame_clusters_per_s":
             b["clusters_per_s"] / b["per_frame_form"]["clusters_per_s"]}
+    a.fp16_min_points = 1024
+    bf = batch_bench(a, torch, binding, synth, dev)
+    out["batched_fp16"] = {
+        "workload": WORKLOAD_TEXT["batched"] + "; FP16 residual form for clusters of at least "
+                    "1024 points (outputs bitwise the float32 form's)",
+        "fp16_min_points": 1024, "ms_per_step": bf["ms_per_step"],
+        "clusters_per_s": bf["clusters_per_s"], "evals_per_s": bf["value"],
+        "stage_ms": bf["stage_ms"], "per_frame_form": bf["per_frame_form"],
+        "over_per_frame_clusters_per_s":
+            bf["clusters_per_s"] / bf["per_frame_form"]["clusters_per_s"]}
     a = copy.copy(args)
     a.no_cpu_baseline = True
     a.workload = "served"
     a.duration = args.extras_duration
-    sv = served_bench(a, torch, binding, synth, dev)
+    a.fp16_min_points = 0
+    sv = served_bench(a, torch, binding, synth, dev, extra_fp16=256)
+    pf = sv["per_frame_form"]
     out["served"] = {
-        "workload": WORKLOAD_TEXT["served"], "duration_s": a.duration,
-        "arrivals": sv["config"]["frames"], "served_form": sv["served_form"],
-        "per_frame_form": sv["per_frame_form"],
+        "workload": WORKLOAD_TEXT["served"] + "; the served form in float32 and in the FP16 "
+                    "residual form for clusters of at least 256 points (outputs bitwise equal), "
+                    "the per-frame form in float32, all on the same arrivals",
+        "duration_s": a.duration, "arrivals": sv["config"]["frames"],
+        "served_form": sv["served_form"], "served_fp16_form": sv["served_fp16_form"],
+        "per_frame_form": pf,
         "served_over_per_frame_clusters_per_s":
-            sv["served_form"]["saturated"]["clusters_per_s"]
-            / sv["per_frame_form"]["saturated"]["clusters_per_s"],
+            sv["served_form"]["saturated"]["clusters_per_s"] / pf["saturated"]["clusters_per_s"],
         "p99_served_over_per_frame":
-            sv["served_form"]["latency_ms"]["p99"] / sv["per_frame_form"]["latency_ms"]["p99"]}
+            sv["served_form"]["latency_ms"]["p99"] / pf["latency_ms"]["p99"],
+        "served_fp16_over_per_frame_clusters_per_s":
+            sv["served_fp16_form"]["saturated"]["clusters_per_s"] / pf["saturated"]["clusters_per_s"],
+        "p99_served_fp16_over_per_frame":
+            sv["served_fp16_form"]["latency_ms"]["p99"] / pf["latency_ms"]["p99"]}
     return out
 
 
