@@ -131,7 +131,7 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
  * every input and output.
  *   - A frame whose rv_workspace_bytes() exceeds RV_NOALLOC_SCRATCH_BYTES is
  *     rejected with RV_ERR_WORKSPACE before anything is enqueued (96 MiB: up to
- *     about 3.5 million points).
+ *     about 5 million points).
  *   - `stream` must belong to the current device (else RV_ERR_INVALID_ARG).
  *   - All calls on one GPU share its array: calls whose work may overlap on
  *     that GPU (different streams, or different threads without ordering) race

@@ -110,14 +110,23 @@ constexpr int64_t kPlanMaxClusters = 1 << 16;  // above this, clusters run in in
 // ---------------------------------------------------------------------------
 
 // Staged points: float32 (cos, sin) and v_d for scoring (v_d = +inf marks a
-// point whose azimuth or Doppler value is not finite), FP64 (cos, sin) for the
-// solves and the refit, and the caller's azimuths for the seed-separation test.
+// point whose azimuth or Doppler value is not finite), the float32 low parts of
+// the FP64 (cos, sin) for the solves and the refit (cs64() below), and the
+// caller's azimuths for the seed-separation test.
 struct Points {
     const float2 *cs32;
     const float *v32;
-    const double2 *cs64;
+    const float2 *cslo;
     const float *theta;
 };
+
+// FP64 (cos, sin) of a staged point: the float32 value plus its float32 low
+// part, c = hi + lo (an exact FP64 sum), within 2^-49 of the FP64 sincos.
+// Staging 8 bytes per point for the low parts instead of 16 for the FP64 pair
+// shortens the staging kernel, which is bound by its bytes.
+__device__ __forceinline__ double2 cs64(float2 hi, float2 lo) {
+    return make_double2((double)hi.x + (double)lo.x, (double)hi.y + (double)lo.y);
+}
 
 struct Hypothesis {
     double vx, vy;
@@ -136,7 +145,7 @@ __device__ __forceinline__ Hypothesis make_hypothesis(const Points &pts, Span sp
     // an invalid pair's solve (possibly inf or NaN) is replaced by NaN.
     const float vi = pts.v32[pi], vj = pts.v32[pj];
     const float ti = pts.theta[pi], tj = pts.theta[pj];
-    const double2 ai = pts.cs64[pi], bj = pts.cs64[pj];
+    const double2 ai = cs64(pts.cs32[pi], pts.cslo[pi]), bj = cs64(pts.cs32[pj], pts.cslo[pj]);
     Hypothesis hy;
     hy.valid = ((int)isfinite(vi) & (int)isfinite(vj) &
                 (int)(fabs((double)tj - (double)ti) >= RV_MIN_SEED_SEPARATION)) != 0;
@@ -173,7 +182,7 @@ __device__ __forceinline__ int size_class(int64_t n) {
 // over the classes (largest first) is one wave's prefix sum, two classes per
 // lane.  This workgroup runs beside the staging workgroups and sets the prep
 // kernel's length when it is the slower one.
-constexpr int kPlanUnroll = 8;
+constexpr int kPlanUnroll = 16;
 static_assert(kSizeClasses == 2 * kWave, "the class scan takes two classes per lane");
 
 // Exclusive prefix sum of x over the lanes of one full wave.
@@ -187,26 +196,10 @@ __device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t x, int lane) {
     return incl - x;
 }
 
-__device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
-                           int64_t n_points, int32_t *__restrict__ order,
-                           int64_t *__restrict__ n_big) {
-    __shared__ uint32_t count[kSizeClasses];
-    __shared__ uint32_t start[kSizeClasses];
-    for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) count[c] = 0;
-    __syncthreads();
-    const int64_t group = (int64_t)kPlanUnroll * kPrepBlock;
-    for (int64_t k0 = threadIdx.x; k0 < n_clusters; k0 += group) {
-        int cls[kPlanUnroll];
-#pragma unroll
-        for (int u = 0; u < kPlanUnroll; ++u) {
-            const int64_t k = k0 + (int64_t)u * kPrepBlock;
-            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < kPlanUnroll; ++u)
-            if (cls[u] >= 0) atomicAdd(&count[cls[u]], 1u);
-    }
-    __syncthreads();
+// Start of each size class in the dispatch order (largest class first) and the
+// number of clusters refit by a whole workgroup; the first wave of the block.
+__device__ __forceinline__ void plan_scan(const uint32_t *count, uint32_t *start,
+                                          int64_t *__restrict__ n_big) {
     if (threadIdx.x < kWave) {
         // Position q = 0, 1, ... in the dispatch order is class kSizeClasses - 1 - q.
         const int lane = threadIdx.x;
@@ -219,6 +212,54 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
         if (c_hi == kRefitBigClass) *n_big = excl + a;
         if (c_lo == kRefitBigClass) *n_big = excl + a + b;
     }
+}
+
+__device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
+                           int64_t n_points, int32_t *__restrict__ order,
+                           int64_t *__restrict__ n_big) {
+    __shared__ uint32_t count[kSizeClasses];
+    __shared__ uint32_t start[kSizeClasses];
+    for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) count[c] = 0;
+    __syncthreads();
+    const int64_t group = (int64_t)kPlanUnroll * kPrepBlock;
+    if (n_clusters <= group) {
+        // One group: every thread's classes stay in registers from the count
+        // to the placement, so the offsets are read once (their loads queue
+        // behind the staging traffic of the other workgroups).
+        int cls[kPlanUnroll];
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u) {
+            const int64_t k = threadIdx.x + (int64_t)u * kPrepBlock;
+            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u)
+            if (cls[u] >= 0) atomicAdd(&count[cls[u]], 1u);
+        __syncthreads();
+        plan_scan(count, start, n_big);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u) {
+            if (cls[u] >= 0) {
+                const uint32_t pos = atomicAdd(&start[cls[u]], 1u);
+                order[pos] = (int32_t)(threadIdx.x + u * kPrepBlock);
+            }
+        }
+        return;
+    }
+    for (int64_t k0 = threadIdx.x; k0 < n_clusters; k0 += group) {
+        int cls[kPlanUnroll];
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u) {
+            const int64_t k = k0 + (int64_t)u * kPrepBlock;
+            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kPlanUnroll; ++u)
+            if (cls[u] >= 0) atomicAdd(&count[cls[u]], 1u);
+    }
+    __syncthreads();
+    plan_scan(count, start, n_big);
     __syncthreads();
     for (int64_t k0 = threadIdx.x; k0 < n_clusters; k0 += group) {
         int cls[kPlanUnroll];
@@ -238,20 +279,22 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
 }
 
 // Stages point p: FP64 sincos of its azimuth, float32 (cos, sin) and v_d for
-// scoring, FP64 (cos, sin) for the solves and the refit.  A non-finite point
-// is staged as (0, 0, +inf): its float32 residual is inf or NaN, never below
-// tau, and +inf marks it for the solves and the refit.
+// scoring, and the float32 low parts of the FP64 (cos, sin) (c - (double)(float)c,
+// rounded) for the solves and the refit.  A non-finite point is staged as
+// (0, 0, +inf) with zero low parts: its float32 residual is inf or NaN, never
+// below tau, and +inf marks it for the solves and the refit.
 __device__ __forceinline__ void stage_point(const float *__restrict__ theta,
                                             const float *__restrict__ vd, int64_t p,
                                             float2 *__restrict__ cs32, float *__restrict__ v32,
-                                            double2 *__restrict__ cs64) {
+                                            float2 *__restrict__ cslo) {
     const float t = theta[p], v = vd[p];
     double s, c;
     sincos((double)t, &s, &c);
     const bool ok = isfinite(t) && isfinite(v);
-    cs32[p] = make_float2(ok ? (float)c : 0.0f, ok ? (float)s : 0.0f);
+    const float ch = ok ? (float)c : 0.0f, sh = ok ? (float)s : 0.0f;
+    cs32[p] = make_float2(ch, sh);
     v32[p] = ok ? v : __builtin_inff();
-    cs64[p] = make_double2(c, s);
+    cslo[p] = make_float2(ok ? (float)(c - (double)ch) : 0.0f, ok ? (float)(s - (double)sh) : 0.0f);
 }
 
 // Block 0 plans the order (when `order` is non-null); it is dispatched first,
@@ -259,7 +302,7 @@ __device__ __forceinline__ void stage_point(const float *__restrict__ theta,
 // points and clear the per-cluster best keys.
 __global__ __launch_bounds__(kPrepBlock) void prep_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
-    float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
+    float2 *__restrict__ cs32, float *__restrict__ v32, float2 *__restrict__ cslo,
     uint32_t *__restrict__ bits,
     int64_t n_words, const int32_t *__restrict__ off, int64_t n_clusters,
     int32_t *__restrict__ order, int64_t *__restrict__ n_big,
@@ -270,7 +313,7 @@ __global__ __launch_bounds__(kPrepBlock) void prep_kernel(
     }
     const int64_t p = (int64_t)(blockIdx.x - 1) * kPrepBlock + threadIdx.x;
     if (p < n_clusters) best_key[p] = 0;
-    if (p < n_points) stage_point(theta, vd, p, cs32, v32, cs64);
+    if (p < n_points) stage_point(theta, vd, p, cs32, v32, cslo);
     if (bits != nullptr && p < n_words) bits[p] = 0u;
 }
 
@@ -998,7 +1041,7 @@ __device__ __forceinline__ RefitSums refit_sweep(Span sp, int64_t first_block, i
     const int64_t end = sp.lo + sp.n;
     for (int64_t p0 = first_block; p0 < end; p0 += kRefitUnroll * stride) {
         float v[kRefitUnroll];
-        double2 cs[kRefitUnroll];
+        float2 hi[kRefitUnroll], lo[kRefitUnroll];
         bool in[kRefitUnroll];
 #pragma unroll
         for (int u = 0; u < kRefitUnroll; ++u) {
@@ -1006,12 +1049,14 @@ __device__ __forceinline__ RefitSums refit_sweep(Span sp, int64_t first_block, i
             in[u] = p >= sp.lo && p < end;
             const int64_t q = in[u] ? p : sp.lo;
             v[u] = pts.v32[q];
-            cs[u] = pts.cs64[q];
+            hi[u] = pts.cs32[q];
+            lo[u] = pts.cslo[q];
         }
 #pragma unroll
         for (int u = 0; u < kRefitUnroll; ++u)
             if (p0 + u * stride < end)
-                refit_points(p0 + u * stride, in[u], v[u], cs[u], hy, dtau, a, o, lane);
+                refit_points(p0 + u * stride, in[u], v[u], cs64(hi[u], lo[u]), hy, dtau, a, o,
+                             lane);
     }
     return a;
 }
@@ -1267,7 +1312,7 @@ __global__ __launch_bounds__(kRefitBlock) void refit_kernel(
 __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))) void small_frame_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd, const int32_t *__restrict__ off,
     int64_t n_points, int32_t n_hyp, uint32_t key0, uint32_t key1, Points pts, float tau,
-    float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
+    float2 *__restrict__ cs32, float *__restrict__ v32, float2 *__restrict__ cslo,
     unsigned long long *__restrict__ best_key, Outputs o) {
     __shared__ float4 s_hyp[kScoreBlock / 2];
     __shared__ unsigned long long s_key[kScoreBlock / kWave];
@@ -1278,7 +1323,7 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     const int64_t k = blockIdx.x;
     const Span sp = cluster_span(off, k, n_points);
     for (int64_t p = sp.lo + threadIdx.x; p < sp.lo + sp.n; p += kScoreBlock)
-        stage_point(theta, vd, p, cs32, v32, cs64);
+        stage_point(theta, vd, p, cs32, v32, cslo);
     if (threadIdx.x == 0) best_key[k] = 0;
     __syncthreads();
     ClusterId id;
@@ -1383,14 +1428,14 @@ __global__ __launch_bounds__(kSizeClasses) void batch_init_kernel(
 // one global atomic per class and block).
 __global__ __launch_bounds__(kPrepBlock) void batch_prep_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
-    float2 *__restrict__ cs32, float *__restrict__ v32, double2 *__restrict__ cs64,
+    float2 *__restrict__ cs32, float *__restrict__ v32, float2 *__restrict__ cslo,
     uint32_t *__restrict__ bits, int64_t n_words, const int32_t *__restrict__ off,
     int64_t n_clusters, unsigned long long *__restrict__ best_key, uint32_t *__restrict__ hist) {
     __shared__ uint32_t local[kSizeClasses];
     for (int c = threadIdx.x; c < kSizeClasses; c += kPrepBlock) local[c] = 0;
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * kPrepBlock + threadIdx.x;
-    if (p < n_points) stage_point(theta, vd, p, cs32, v32, cs64);
+    if (p < n_points) stage_point(theta, vd, p, cs32, v32, cslo);
     if (bits != nullptr && p < n_words) bits[p] = 0u;
     if (p < n_clusters) {
         best_key[p] = 0;
@@ -1574,7 +1619,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t cs32, v32, cs64, order, best_key, n_big, total;
+    size_t cs32, v32, cslo, order, best_key, n_big, total;
 };
 
 Layout make_layout(int64_t n_clusters, int64_t n_points) {
@@ -1583,7 +1628,7 @@ Layout make_layout(int64_t n_clusters, int64_t n_points) {
     size_t at = 0;
     L.cs32 = at; at = align_up(at + np * sizeof(float2));
     L.v32 = at; at = align_up(at + np * sizeof(float));
-    L.cs64 = at; at = align_up(at + np * sizeof(double2));
+    L.cslo = at; at = align_up(at + np * sizeof(float2));
     L.order = at; at = align_up(at + (size_t)n_clusters * sizeof(int32_t));
     L.best_key = at; at = align_up(at + (size_t)n_clusters * sizeof(unsigned long long));
     L.n_big = at; at = align_up(at + sizeof(int64_t));
@@ -1595,7 +1640,7 @@ Layout make_layout(int64_t n_clusters, int64_t n_points) {
 
 
 struct BatchLayout {
-    size_t cs32, v32, cs64, desc, best_key, hist, queues, n_big, total;
+    size_t cs32, v32, cslo, desc, best_key, hist, queues, n_big, total;
 };
 
 BatchLayout make_batch_layout(int64_t n_clusters, int64_t n_points) {
@@ -1604,7 +1649,7 @@ BatchLayout make_batch_layout(int64_t n_clusters, int64_t n_points) {
     size_t at = 0;
     L.cs32 = at; at = align_up(at + np * sizeof(float2));
     L.v32 = at; at = align_up(at + np * sizeof(float));
-    L.cs64 = at; at = align_up(at + np * sizeof(double2));
+    L.cslo = at; at = align_up(at + np * sizeof(float2));
     L.desc = at; at = align_up(at + nc * sizeof(ItemDesc));
     L.best_key = at; at = align_up(at + nc * sizeof(unsigned long long));
     L.hist = at; at = align_up(at + kSizeClasses * sizeof(uint32_t));
@@ -1720,7 +1765,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     char *ws = (char *)a.workspace;
     float2 *cs32 = (float2 *)(ws + L.cs32);
     float *v32 = (float *)(ws + L.v32);
-    double2 *cs64 = (double2 *)(ws + L.cs64);
+    float2 *cslo = (float2 *)(ws + L.cslo);
     ItemDesc *desc = (ItemDesc *)(ws + L.desc);
     unsigned long long *best_key = (unsigned long long *)(ws + L.best_key);
     uint32_t *hist = (uint32_t *)(ws + L.hist);
@@ -1729,7 +1774,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     Points pts;
     pts.cs32 = cs32;
     pts.v32 = v32;
-    pts.cs64 = cs64;
+    pts.cslo = cslo;
     pts.theta = a.theta;
     Batch bt;
     bt.frame_off = a.frame_off;
@@ -1749,7 +1794,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
     if (timed) (void)hipEventRecord(tc.ev[0], st);
     hipLaunchKernelGGL(batch_init_kernel, dim3(1), dim3(kSizeClasses), 0, st, hist, queues);
     hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)((prep_items + kPrepBlock - 1) / kPrepBlock)),
-                       dim3(kPrepBlock), 0, st, a.theta, a.vd, a.n_points, cs32, v32, cs64,
+                       dim3(kPrepBlock), 0, st, a.theta, a.vd, a.n_points, cs32, v32, cslo,
                        a.o.bits, n_words, a.off, a.n_clusters, best_key, hist);
     hipLaunchKernelGGL(batch_scan_kernel, dim3(1), dim3(64), 0, st, hist, n_big);
     hipLaunchKernelGGL(batch_scatter_kernel,
@@ -1864,11 +1909,11 @@ int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_o
     char *ws = (char *)workspace;
     float2 *cs32 = (float2 *)(ws + L.cs32);
     float *v32 = (float *)(ws + L.v32);
-    double2 *cs64 = (double2 *)(ws + L.cs64);
+    float2 *cslo = (float2 *)(ws + L.cslo);
     Points pts;
     pts.cs32 = cs32;
     pts.v32 = v32;
-    pts.cs64 = cs64;
+    pts.cslo = cslo;
     pts.theta = theta;
     int32_t *order = n_clusters <= kPlanMaxClusters ? (int32_t *)(ws + L.order) : nullptr;
     int64_t *n_big = (int64_t *)(ws + L.n_big);
@@ -1896,7 +1941,7 @@ int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_o
         if (timed) (void)hipEventRecord(tc.ev[1], st);
         hipLaunchKernelGGL(small_frame_kernel, dim3((unsigned)n_clusters), dim3(kScoreBlock), 0, st,
                            theta, vd, cluster_offsets, n_points, n_hyp, key0, key1, pts, tau, cs32,
-                           v32, cs64, best_key, o);
+                           v32, cslo, best_key, o);
         if (timed) {
             (void)hipEventRecord(tc.ev[2], st);
             (void)hipEventRecord(tc.ev[3], st);
@@ -1910,7 +1955,7 @@ int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_o
     prep_items = prep_items > n_clusters ? prep_items : n_clusters;
     const int64_t prep_blocks = (prep_items + kPrepBlock - 1) / kPrepBlock + 1;  // + planner
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)prep_blocks), dim3(kPrepBlock), 0, st, theta,
-                       vd, n_points, cs32, v32, cs64, inlier_bits, n_words, cluster_offsets,
+                       vd, n_points, cs32, v32, cslo, inlier_bits, n_words, cluster_offsets,
                        n_clusters, order, n_big, best_key);
     if (timed) (void)hipEventRecord(tc.ev[1], st);
     hipLaunchKernelGGL(score_kernel, dim3((unsigned)(clusters_xcd * blocks_per_cluster)),

@@ -58,7 +58,7 @@ def test_noalloc_scratch_limit(lib):
     assert "RV_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)" in text
     assert binding.RV_NOALLOC_SCRATCH_BYTES == 96 << 20
     fake = ctypes.c_void_p(4096)
-    n = 3_600_000
+    n = 5_500_000
     assert binding.rv_workspace_bytes(1, n, 64) > binding.RV_NOALLOC_SCRATCH_BYTES
     assert binding.rv_workspace_bytes(4096, 2_723_399, 1024) <= binding.RV_NOALLOC_SCRATCH_BYTES
     rc = lib.rv_estimate_velocity_noalloc(fake, fake, fake, 1, n, 64, 0.15, 1, fake, fake, fake,
@@ -74,8 +74,8 @@ def test_workspace_bytes(lib):
     b = binding.rv_workspace_bytes(4096, 2_700_000, 1024)
     assert 0 < a < b
     assert binding.rv_workspace_bytes(-1, 10, 8) == 0
-    # 28 bytes per point (float2 + float + double2) and 12 per cluster, 256-byte aligned sections
-    assert 28 * 2_700_000 + 12 * 4096 <= b <= 28 * 2_700_000 + 12 * 4096 + 6 * 256
+    # 20 bytes per point (float2 + float + float2) and 12 per cluster, 256-byte aligned sections
+    assert 20 * 2_700_000 + 12 * 4096 <= b <= 20 * 2_700_000 + 12 * 4096 + 6 * 256
     assert binding.rv_workspace_bytes(4096, 2_700_000, 1) == b  # independent of n_hyp
     assert b % 256 == 0
 
@@ -220,10 +220,10 @@ def test_server_host_checks(lib):
     cfg = binding.rv_server_config_default()
     assert (cfg.n_hyp, cfg.max_batch_frames, cfg.n_streams) == (512, 64, 2)
     assert cfg.hbm_budget_bytes == 16 << 30
-    # arena bytes of one frame: 36 per point (inputs 8, staging 28) and 69 per cluster
+    # arena bytes of one frame: 28 per point (inputs 8, staging 20) and 69 per cluster
     # (offsets 4, descriptor 32, best key 8, outputs 25), plus 256-byte sections and queues
     b = binding.rv_server_frame_bytes(cfg, 700, 146_000)
-    assert 36 * 146_000 + 69 * 700 <= b <= 36 * 146_000 + 69 * 700 + 25 * 256 + 2560
+    assert 28 * 146_000 + 69 * 700 <= b <= 28 * 146_000 + 69 * 700 + 25 * 256 + 2560
     # with the inlier masks kept: one more bit per point
     cfg.keep_inlier_bits = 1
     bm = binding.rv_server_frame_bytes(cfg, 700, 146_000)

@@ -80,7 +80,7 @@ def test_noalloc_matches_workspace_entry_point(rv, oracle_mod):
 
 
 def test_noalloc_refuses_a_frame_beyond_its_scratch(rv):
-    n = 3_600_000
+    n = 5_500_000
     assert rv.rv_workspace_bytes(1, n, 64) > rv.RV_NOALLOC_SCRATCH_BYTES
     t = torch.zeros(n, dtype=torch.float32, device="cuda")
     o = torch.tensor([0, n], dtype=torch.int32, device="cuda")
