@@ -1031,32 +1031,46 @@ __device__ __forceinline__ void refit_points(int64_t p0, bool in_range, float v,
 // steps of `stride`, kRefitUnroll blocks per iteration: the loads of all of
 // them are issued (from a clamped, always valid index) before any block is
 // used.  Each lane visits its points in the same order as one block per
-// iteration, so the sums are the same.
+// iteration, so the sums are the same.  The first iteration's loads do not
+// depend on h*: the callers issue them (refit_load) before solving h*, so
+// their latency overlaps the hypothesis's.
 constexpr int kRefitUnroll = 4;
 
+struct RefitLoads {
+    float v[kRefitUnroll];
+    float2 hi[kRefitUnroll], lo[kRefitUnroll];
+    bool in[kRefitUnroll];
+};
+
+__device__ __forceinline__ RefitLoads refit_load(Span sp, int64_t p0, int64_t stride,
+                                                 const Points &pts, int lane) {
+    RefitLoads L;
+    const int64_t end = sp.lo + sp.n;
+#pragma unroll
+    for (int u = 0; u < kRefitUnroll; ++u) {
+        const int64_t p = p0 + u * stride + lane;
+        L.in[u] = p >= sp.lo && p < end;
+        const int64_t q = L.in[u] ? p : sp.lo;
+        L.v[u] = pts.v32[q];
+        L.hi[u] = pts.cs32[q];
+        L.lo[u] = pts.cslo[q];
+    }
+    return L;
+}
+
 __device__ __forceinline__ RefitSums refit_sweep(Span sp, int64_t first_block, int64_t stride,
-                                                 const Points &pts, const Hypothesis &hy,
-                                                 double dtau, const Outputs &o, int lane) {
+                                                 const RefitLoads &first, const Points &pts,
+                                                 const Hypothesis &hy, double dtau,
+                                                 const Outputs &o, int lane) {
     RefitSums a;
     const int64_t end = sp.lo + sp.n;
     for (int64_t p0 = first_block; p0 < end; p0 += kRefitUnroll * stride) {
-        float v[kRefitUnroll];
-        float2 hi[kRefitUnroll], lo[kRefitUnroll];
-        bool in[kRefitUnroll];
-#pragma unroll
-        for (int u = 0; u < kRefitUnroll; ++u) {
-            const int64_t p = p0 + u * stride + lane;
-            in[u] = p >= sp.lo && p < end;
-            const int64_t q = in[u] ? p : sp.lo;
-            v[u] = pts.v32[q];
-            hi[u] = pts.cs32[q];
-            lo[u] = pts.cslo[q];
-        }
+        const RefitLoads L = p0 == first_block ? first : refit_load(sp, p0, stride, pts, lane);
 #pragma unroll
         for (int u = 0; u < kRefitUnroll; ++u)
             if (p0 + u * stride < end)
-                refit_points(p0 + u * stride, in[u], v[u], cs64(hi[u], lo[u]), hy, dtau, a, o,
-                             lane);
+                refit_points(p0 + u * stride, L.in[u], L.v[u], cs64(L.hi[u], L.lo[u]), hy, dtau,
+                             a, o, lane);
     }
     return a;
 }
@@ -1081,14 +1095,14 @@ __device__ __forceinline__ void refit_block(Span sp, ClusterId id, unsigned long
         if (tid == 0) write_failed(o, k, RV_CLUSTER_ALL_DEGENERATE);
         return;
     }
+    // Waves walk 64-aligned global blocks so one wave ballot maps onto two
+    // words of the frame-wide bitmask.
+    const int64_t first_block = (sp.lo & ~(int64_t)(kWave - 1)) + (int64_t)wave * kWave;
+    const RefitLoads first = refit_load(sp, first_block, kRefitBlock, pts, lane);
     const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
     const Hypothesis hy = make_hypothesis(pts, sp, hbest, id.local, id.key0, id.key1);
     const double dtau = tau;
-
-    // Waves walk 64-aligned global blocks so one wave ballot maps onto two
-    // words of the frame-wide bitmask.
-    const RefitSums a = refit_sweep(sp, (sp.lo & ~(int64_t)(kWave - 1)) + (int64_t)wave * kWave,
-                                    kRefitBlock, pts, hy, dtau, o, lane);
+    const RefitSums a = refit_sweep(sp, first_block, kRefitBlock, first, pts, hy, dtau, o, lane);
     double scc = a.scc, scs = a.scs, sss = a.sss, scv = a.scv, ssv = a.ssv;
     int n_in = a.n_in, n_near = a.n_near;
     scc = wave_sum(scc);
@@ -1163,13 +1177,14 @@ __device__ __forceinline__ void refit_wave(Span sp, ClusterId id, unsigned long 
         if (lane == 0) write_failed(o, k, RV_CLUSTER_ALL_DEGENERATE);
         return;
     }
+    // 64-aligned global blocks of points, so one ballot maps onto two words of
+    // the frame-wide bitmask.
+    const int64_t first_block = sp.lo & ~(int64_t)(kWave - 1);
+    const RefitLoads first = refit_load(sp, first_block, kWave, pts, lane);
     const uint32_t hbest = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
     const Hypothesis hy = make_hypothesis(pts, sp, hbest, id.local, id.key0, id.key1);
     const double dtau = tau;
-
-    // 64-aligned global blocks of points, so one ballot maps onto two words of
-    // the frame-wide bitmask.
-    const RefitSums a = refit_sweep(sp, sp.lo & ~(int64_t)(kWave - 1), kWave, pts, hy, dtau, o, lane);
+    const RefitSums a = refit_sweep(sp, first_block, kWave, first, pts, hy, dtau, o, lane);
     double scc = a.scc, scs = a.scs, sss = a.sss, scv = a.scv, ssv = a.ssv;
     int n_in = a.n_in, n_near = a.n_near;
     scc = wave_sum(scc);
