@@ -671,7 +671,7 @@ def paper_sweep_bench(args, torch, binding, synth, dev) -> int:
     return 0
 
 
-def precision_bench(args, torch, binding, synth, dev) -> int:
+def precision_bench(args, torch, binding, synth, dev, oracle_budget_s: float = 10.0) -> dict:
     """Precision-stress shape: the FP16 residual form against the float32 form
     on the same frame (both through the batched entry point, one frame), every
     output compared bitwise, and the FP64 oracle on sampled clusters."""
@@ -732,7 +732,7 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
     ids, dt, rounds = [], 0.0, []
     g = forms["fp16"]["res"]
     o_parts = []
-    while len(ids) < K and (dt < 10.0 or not ids):
+    while len(ids) < K and (dt < oracle_budget_s or not ids):
         chunk = order[len(ids):len(ids) + threads]
         print(f"[bench] oracle on clusters {chunk[0]}.. ({len(ids) + len(chunk)}/{K}), {threads} threads",
               file=sys.stderr, flush=True)
@@ -795,8 +795,7 @@ def precision_bench(args, torch, binding, synth, dev) -> int:
                      "note": "the MI355X vector FP16 and FP32 peaks are the same 157.3 TFLOP/s"},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
-    return 0 if identical else 1
+    return line
 
 
 def fp16_recount_stats(hi, exact, sizes, n_hyp, block=256):
@@ -1027,8 +1026,10 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
     that one run reports them all: the small frame (the paper's Table I shape:
     per-step time and latency over 1000 distinct frames), the 256-frame batched
     form (one graph replay per step, and the per-frame form on the same
-    frames, in the float32 form and in the FP16 residual form), and the served
-    form at 64 radars x 20 frames/s (latency and saturated throughput of the
+    frames, in the float32 form and in the FP16 residual form), the precision
+    stress shape (the FP16 residual form against the float32 form, errors
+    against the FP64 oracle on a sample of clusters), and the served form at
+    64 radars x 20 frames/s (latency and saturated throughput of the
     served and the per-frame forms; the served form in float32, then in the FP16
     residual form)."""
     import copy
@@ -1067,6 +1068,17 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
         "stage_ms": bf["stage_ms"], "per_frame_form": bf["per_frame_form"],
         "over_per_frame_clusters_per_s":
             bf["clusters_per_s"] / bf["per_frame_form"]["clusters_per_s"]}
+    a = copy.copy(args)
+    a.no_cpu_baseline = True
+    a.workload = "precision"
+    a.steps, a.warmup, a.fp16_min_points = 3, 1, 0
+    pr = precision_bench(a, torch, binding, synth, dev, oracle_budget_s=4.0)
+    out["precision"] = {k: pr[k] for k in (
+        "ms_per_step", "clusters_per_s", "fp32_form", "fp16_over_fp32_time",
+        "outputs_bitwise_equal_to_fp32_form", "fp16_recount", "oracle_error", "stage_ms",
+        "roofline")}
+    out["precision"].update({"workload": WORKLOAD_TEXT["precision"], "evals_per_s": pr["value"],
+                             "fp16_min_points": pr["config"]["fp16_min_points"]})
     a = copy.copy(args)
     a.no_cpu_baseline = True
     a.workload = "served"
@@ -1181,7 +1193,9 @@ def main() -> int:
     if name == "paper-sweep":
         return paper_sweep_bench(args, torch, binding, synth, dev)
     if name == "precision":
-        return precision_bench(args, torch, binding, synth, dev)
+        line = precision_bench(args, torch, binding, synth, dev)
+        print(json.dumps(line), flush=True)
+        return 0 if line["outputs_bitwise_equal_to_fp32_form"] else 1
     if name not in FRAME_WORKLOADS:
         line = batch_bench(args, torch, binding, synth, dev)
     else:
