@@ -125,9 +125,10 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
  * hipMalloc.  rv_estimate_velocity_noalloc takes the arguments of
  * rv_estimate_velocity without the workspace and gives the same results bit
  * for bit (same kernels).  Its workspace is a device array of
- * RV_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from the first
- * such call on that GPU until the process ends; the call itself allocates and
- * frees nothing and records no stage-timing events.  The caller still owns
+ * RV_NOALLOC_SCRATCH_BYTES inside the library's code object: each GPU holds its
+ * own copy from the library's first use on that GPU (the code object's load,
+ * whichever entry point causes it) until the process ends.  The call itself
+ * allocates and frees nothing and records no stage-timing events.  The caller still owns
  * every input and output.
  *   - A frame whose rv_workspace_bytes() exceeds RV_NOALLOC_SCRATCH_BYTES is
  *     rejected with RV_ERR_WORKSPACE before anything is enqueued (96 MiB: up to

@@ -1997,8 +1997,8 @@ int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_o
 // ---- Allocation-free single-frame entry point ------------------------------
 //
 // rv_estimate_velocity_noalloc keeps its workspace in `scratch`, a device array
-// of RV_NOALLOC_SCRATCH_BYTES that each GPU holds from the first such call on it
-// until the process ends.  In host code the array's name denotes a host-side
+// of RV_NOALLOC_SCRATCH_BYTES that each GPU holds from the load of this code
+// object on it until the process ends.  In host code the array's name denotes a host-side
 // stand-in, not device memory: host code only passes on the address that
 // hipGetSymbolAddress returns for the current device, looked up once per device
 // and kept in g_scratch.  Every kernel writes the parts of the workspace it
