@@ -246,7 +246,8 @@ def sum_evals(frame, n_hyp):
     return synth.evals_per_frame(frame.offsets, n_hyp)
 
 
-def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_frames):
+def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_frames,
+                zero_copy=False):
     """Host-clock latency of n_frames distinct frames, each from pinned host
     memory through the H2D copies, the estimate and the D2H copies of the
     per-cluster results (synchronised per frame).  Frame i is drawn fresh for
@@ -255,11 +256,12 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
     draws) with every azimuth turned by a distinct angle of at most 0.062 rad,
     so that no two timed frames are equal.  Each frame is written into the
     pinned buffer before its clock starts.  Returns (milliseconds per frame,
-    recipe text)."""
+    recipe text, and with zero_copy the milliseconds per frame of the same frames
+    estimated straight from and into pinned host memory, else None)."""
     import numpy as np
 
     if n_frames <= 0:
-        return [], None
+        return [], None, None
     spec = synth.WORKLOADS[name][0]
     if name == "small":
         bases = [synth.make_frame(spec, 100_000 + i) for i in range(n_frames)]
@@ -310,7 +312,33 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
     for i in range(min(8, n_frames)):  # untimed first use of the buffers
         one(i, synth.ransac_seed(name, 9_000 + i))
     lat = [one(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
-    return lat, recipe
+    if not zero_copy:
+        return lat, recipe, None
+
+    # The same frames with no copies: inputs and outputs in pinned host memory,
+    # read and written by the kernels through their device mapping, one
+    # prepared call per frame (the buffers hold the largest frame).
+    z_out = binding.allocate_outputs(k_max, n_max, n_hyp, "cpu", want_near=True)
+    z_ws = out["workspace"]
+    z_out = {key: (v.pin_memory() if key != "workspace" else z_ws) for key, v in z_out.items()}
+    prep = binding.PreparedEstimate(h_t, h_v, h_o, n_hyp, tau, z_out, stream=stream)
+
+    def zero(i, seed):
+        th, vd, off = frame_at(i)
+        n, k = th.shape[0], off.shape[0] - 1
+        h_t[:n].numpy()[:] = th
+        h_v[:n].numpy()[:] = vd
+        h_o[:k + 1].numpy()[:] = off
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prep(seed, n_points=n, n_clusters=k)
+        stream.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    for i in range(min(8, n_frames)):
+        zero(i, synth.ransac_seed(name, 9_000 + i))
+    lat_z = [zero(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    return lat, recipe, lat_z
 
 
 def batch_bench(args, torch, binding, synth, dev) -> dict:
@@ -944,8 +972,10 @@ def frame_bench(args, torch, binding, synth, dev, name) -> dict:
 
     # Frame latency: pinned host frame -> device -> estimate -> results in host memory.
     print(f"[bench] latency over {args.latency_frames} distinct frames", file=sys.stderr, flush=True)
-    lat, lat_recipe = latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau,
-                                  args.latency_frames)
+    # Small frames also straight from and into pinned host memory (no copies);
+    # a large frame would send its seed-azimuth reads over PCIe, so it is copied.
+    lat, lat_recipe, lat_z = latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp,
+                                         tau, args.latency_frames, zero_copy=small_path)
 
     calibration_copy(torch, dev, args.copy_calibration_mb)
 
@@ -1005,6 +1035,12 @@ def frame_bench(args, torch, binding, synth, dev, name) -> dict:
                         "distinct_frames": len(lat), "frames_recipe": lat_recipe,
                         "scope": "pinned host frame -> H2D -> estimate -> D2H of per-cluster results"}
                        if lat else None),
+        "latency_zero_copy_ms": ({"p50": percentile(lat_z, 50), "p99": percentile(lat_z, 99),
+                                  "frames": len(lat_z), "frames_recipe": lat_recipe,
+                                  "scope": "pinned host frame -> estimate reading the inputs and "
+                                           "writing the per-cluster results in pinned host memory "
+                                           "through their device mapping (no copies)"}
+                                 if lat_z else None),
         "step_ms": {"median": percentile(step_times, 50), "p99": percentile(step_times, 99),
                     "scope": "single steps, a second pass with an event between steps"},
         "stage_ms": dict(zip(binding.STAGE_NAMES, stage_avg)),
@@ -1042,7 +1078,8 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
     out["small_frame"] = {
         "workload": WORKLOAD_TEXT["small"], "ms_per_step": small["ms_per_step"],
         "clusters_per_s": small["clusters_per_s"], "evals_per_s": small["value"],
-        "latency_ms": small["latency_ms"], "kernel": small["roofline"]["kernel"],
+        "latency_ms": small["latency_ms"],
+        "latency_zero_copy_ms": small["latency_zero_copy_ms"], "kernel": small["roofline"]["kernel"],
         "kernel_ms": small["roofline"]["kernel_ms"]}
     a = copy.copy(args)
     a.no_cpu_baseline = True

@@ -394,6 +394,23 @@ int rv_stage_timing(int enable);
 int rv_stage_times(double *ms, int64_t *n_calls);
 
 /*
+ * Pinned host memory as estimate arguments.  Host memory from hipHostMalloc
+ * (which is what torch's pin_memory() allocates) is mapped into the GPUs'
+ * address space: the estimate entry points may read their inputs from it and
+ * write their outputs to it directly, over PCIe, with no copies.  For small
+ * frames, whose copies cost more than the kernels, this shortens the latency
+ * from a frame in host memory to its results in host memory; the workspace
+ * stays in device memory.  rv_host_device_pointer returns in *device_ptr the
+ * address under which the current device sees host_ptr (an address inside a
+ * hipHostMalloc allocation), or RV_ERR_INVALID_ARG (and NULL) when host_ptr is
+ * not in such memory: pageable host memory must never be passed to the
+ * kernels.  The caller keeps the memory allocated while the work that uses it
+ * is in flight, writes inputs before the call and reads outputs only after
+ * synchronising the stream.
+ */
+int rv_host_device_pointer(const void *host_ptr, void **device_ptr);
+
+/*
  * Test hook: n independent Philox4x32-10 blocks computed on the GPU by the same
  * device function the estimator uses.  ctr[4n], key[2n], out[4n] are device
  * arrays of uint32 (block t uses ctr[4t..4t+3] and key[2t..2t+1]).  Enqueued on

@@ -125,6 +125,8 @@ def load_library() -> ctypes.CDLL:
         P, P, P, i64, i64, i32, ctypes.c_float, ctypes.c_uint64,
         P, P, P, P, P, P, P, P, P, P,
     ]
+    lib.rv_host_device_pointer.restype = ctypes.c_int
+    lib.rv_host_device_pointer.argtypes = [P, P]
     lib.rv_last_error.restype = ctypes.c_char_p
     lib.rv_last_error.argtypes = []
     lib.rv_stage_timing.restype = ctypes.c_int
@@ -185,14 +187,32 @@ def rv_workspace_bytes(n_clusters: int, n_points: int, n_hyp: int) -> int:
     return int(load_library().rv_workspace_bytes(int(n_clusters), int(n_points), int(n_hyp)))
 
 
+def host_device_pointer(t: torch.Tensor) -> int:
+    """The address under which the current GPU sees a pinned host tensor's
+    memory (rv_host_device_pointer); raises for pageable memory."""
+    out = ctypes.c_void_p()
+    _check(load_library().rv_host_device_pointer(ctypes.c_void_p(t.data_ptr()), ctypes.byref(out)))
+    return int(out.value)
+
+
 def _dev_ptr(t: torch.Tensor | None, dtype: torch.dtype, device: torch.device, name: str,
-             numel: int | None = None):
+             numel: int | None = None, host_ok: bool = False):
     """Device pointer of a checked tensor; ``numel``: the elements the kernels
-    write or read through it (a smaller tensor raises before anything runs)."""
+    write or read through it (a smaller tensor raises before anything runs).
+    ``host_ok``: a pinned host tensor is accepted too, and the kernels then read
+    or write it directly through its device mapping."""
     if t is None:
         return None
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if host_ok and t.device.type == "cpu":
+        if not t.is_pinned():
+            raise ValueError(f"{name}: host tensors must be pinned (pin_memory())")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if numel is not None and t.numel() < numel:
+            raise ValueError(f"{name} holds {t.numel()} elements, {numel} needed")
+        return ctypes.c_void_p(host_device_pointer(t)) if t.numel() > 0 else None
     if t.device != device:
         raise ValueError(f"{name} must be on {device}, got {t.device}")
     if not t.is_contiguous():
@@ -202,22 +222,33 @@ def _dev_ptr(t: torch.Tensor | None, dtype: torch.dtype, device: torch.device, n
     return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None
 
 
-def _output_ptrs(out: dict, device, n_clusters: int, n_points: int, n_hyp: int) -> tuple:
+def _output_ptrs(out: dict, device, n_clusters: int, n_points: int, n_hyp: int,
+                 host_ok: bool = False) -> tuple:
     """The output pointers of the estimate entry points, in their C order
     (vx, vy, heading, n_inliers, status, n_near_tau, inlier_bits, hyp_counts,
     best_hyp), each checked for dtype, device, layout and size."""
     K = n_clusters
+    h = host_ok
     return (
-        _dev_ptr(out["vx"], torch.float32, device, "vx", K),
-        _dev_ptr(out["vy"], torch.float32, device, "vy", K),
-        _dev_ptr(out["heading"], torch.float32, device, "heading", K),
-        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers", K),
-        _dev_ptr(out["status"], torch.uint8, device, "status", K),
-        _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau", K),
-        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits", (n_points + 31) // 32),
-        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts", K * int(n_hyp)),
-        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp", K),
+        _dev_ptr(out["vx"], torch.float32, device, "vx", K, h),
+        _dev_ptr(out["vy"], torch.float32, device, "vy", K, h),
+        _dev_ptr(out["heading"], torch.float32, device, "heading", K, h),
+        _dev_ptr(out["n_inliers"], torch.int32, device, "n_inliers", K, h),
+        _dev_ptr(out["status"], torch.uint8, device, "status", K, h),
+        _dev_ptr(out.get("n_near_tau"), torch.int32, device, "n_near_tau", K, h),
+        _dev_ptr(out.get("inlier_bits"), torch.int32, device, "inlier_bits", (n_points + 31) // 32, h),
+        _dev_ptr(out.get("hyp_counts"), torch.int32, device, "hyp_counts", K * int(n_hyp), h),
+        _dev_ptr(out.get("best_hyp"), torch.int32, device, "best_hyp", K, h),
     )
+
+
+def _call_device(theta: torch.Tensor) -> torch.device:
+    """The GPU a call runs on: theta's, or the current one for a pinned host theta."""
+    if theta.device.type == "cuda":
+        return theta.device
+    if theta.is_pinned():
+        return torch.device("cuda", torch.cuda.current_device())
+    raise ValueError("theta must be a GPU tensor or a pinned host tensor")
 
 
 def allocate_outputs(n_clusters: int, n_points: int, n_hyp: int, device, *,
@@ -259,8 +290,11 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     """Per-cluster (vx, vy, heading, n_inliers, status) of one CSR frame.
 
     ``theta``/``vd``: float32 [N] on a GPU; ``offsets``: int32 [K+1] on the same
-    device.  Outputs (and the workspace) are allocated with torch unless ``out``
-    (from ``allocate_outputs``) is given.  Work is enqueued on ``stream`` (default:
+    device.  Inputs and the tensors of ``out`` may instead be pinned host
+    tensors (the kernels then read and write them directly, no copies; the
+    call runs on the current GPU and the workspace stays there).  Outputs (and
+    the workspace) are allocated with torch unless ``out`` (from
+    ``allocate_outputs``) is given.  Work is enqueued on ``stream`` (default:
     torch's current stream); the returned tensors are ready after that stream
     synchronises.  ``validate`` checks the offsets on the host first (a device
     to host copy; off by default).  Returned dict keys: vx, vy, heading,
@@ -268,9 +302,7 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     bit p%32 of word p/32 is point p), hyp_counts [K*H], best_hyp.
     """
     lib = load_library()
-    device = theta.device
-    if device.type != "cuda":
-        raise ValueError("theta must be a GPU tensor")
+    device = _call_device(theta)
     n_points = int(theta.numel())
     n_clusters = int(offsets.numel()) - 1
     if n_clusters < 0:
@@ -289,12 +321,13 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     if stream is None:
         stream = torch.cuda.current_stream(device)
     code = lib.rv_estimate_velocity(
-        _dev_ptr(theta, torch.float32, device, "theta"),
-        _dev_ptr(vd, torch.float32, device, "vd"),
-        _dev_ptr(offsets, torch.int32, device, "offsets"),
+        _dev_ptr(theta, torch.float32, device, "theta", host_ok=True),
+        _dev_ptr(vd, torch.float32, device, "vd", host_ok=True),
+        _dev_ptr(offsets, torch.int32, device, "offsets", host_ok=True),
         n_clusters, n_points, int(n_hyp), float(tau), int(seed) & 0xFFFFFFFFFFFFFFFF,
-        *_output_ptrs(out, device, n_clusters, n_points, n_hyp),
-        ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream),
+        *_output_ptrs(out, device, n_clusters, n_points, n_hyp, host_ok=True),
+        _dev_ptr(ws, torch.uint8, device, "workspace"), int(ws.numel()),
+        ctypes.c_void_p(stream.cuda_stream),
     )
     _check(code)
     if owned:
@@ -336,14 +369,15 @@ class PreparedEstimate:
     """rv_estimate_velocity with its tensors checked and their device pointers
     taken once: each call passes only the seed, for callers that estimate frame
     after frame in the same buffers (the tensors' contents may change between
-    calls, not their storage).  Holds references to every tensor it uses."""
+    calls, not their storage).  The tensors may be pinned host tensors, as for
+    rv_estimate_velocity.  A call may also estimate a smaller frame held at the
+    start of the same buffers (n_points, n_clusters up to the prepared sizes).
+    Holds references to every tensor it uses."""
 
     def __init__(self, theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor, n_hyp: int,
                  tau: float, out: dict, stream: torch.cuda.Stream | None = None):
         self._lib = load_library()
-        device = theta.device
-        if device.type != "cuda":
-            raise ValueError("theta must be a GPU tensor")
+        device = _call_device(theta)
         n_points = int(theta.numel())
         n_clusters = int(offsets.numel()) - 1
         if n_clusters < 0 or int(vd.numel()) != n_points:
@@ -352,19 +386,30 @@ class PreparedEstimate:
             stream = torch.cuda.current_stream(device)
         ws = out["workspace"]
         self._keep = (theta, vd, offsets, dict(out), stream)
-        self._head = (
-            _dev_ptr(theta, torch.float32, device, "theta"),
-            _dev_ptr(vd, torch.float32, device, "vd"),
-            _dev_ptr(offsets, torch.int32, device, "offsets"),
-            n_clusters, n_points, int(n_hyp), float(tau))
+        self._ptrs = (
+            _dev_ptr(theta, torch.float32, device, "theta", host_ok=True),
+            _dev_ptr(vd, torch.float32, device, "vd", host_ok=True),
+            _dev_ptr(offsets, torch.int32, device, "offsets", host_ok=True))
+        self._sizes = (n_clusters, n_points)
+        self._scalars = (int(n_hyp), float(tau))
         self._tail = (
-            *_output_ptrs(out, device, n_clusters, n_points, n_hyp),
-            ctypes.c_void_p(ws.data_ptr()), int(ws.numel()), ctypes.c_void_p(stream.cuda_stream))
+            *_output_ptrs(out, device, n_clusters, n_points, n_hyp, host_ok=True),
+            _dev_ptr(ws, torch.uint8, device, "workspace"), int(ws.numel()),
+            ctypes.c_void_p(stream.cuda_stream))
         self.out = {k: v for k, v in out.items() if k != "workspace"}
 
-    def __call__(self, seed: int) -> dict:
-        _check(self._lib.rv_estimate_velocity(*self._head, int(seed) & 0xFFFFFFFFFFFFFFFF,
-                                              *self._tail))
+    def __call__(self, seed: int, n_points: int | None = None,
+                 n_clusters: int | None = None) -> dict:
+        k, n = self._sizes
+        if n_clusters is not None or n_points is not None:
+            k1 = k if n_clusters is None else int(n_clusters)
+            n1 = n if n_points is None else int(n_points)
+            if not (0 <= k1 <= k and 0 <= n1 <= n):
+                raise ValueError(f"a frame of {k1} clusters and {n1} points does not fit the "
+                                 f"prepared {k} and {n}")
+            k, n = k1, n1
+        _check(self._lib.rv_estimate_velocity(*self._ptrs, k, n, *self._scalars,
+                                              int(seed) & 0xFFFFFFFFFFFFFFFF, *self._tail))
         return self.out
 
 

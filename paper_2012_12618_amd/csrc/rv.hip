@@ -2122,6 +2122,28 @@ int rv_stage_times(double *ms, int64_t *n_calls) {
     return rc;
 }
 
+int rv_host_device_pointer(const void *host_ptr, void **device_ptr) {
+    g_error[0] = '\0';
+    if (device_ptr == nullptr) return fail(RV_ERR_INVALID_ARG, "device_ptr is NULL");
+    *device_ptr = nullptr;
+    if (host_ptr == nullptr) return fail(RV_ERR_INVALID_ARG, "host_ptr is NULL");
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, host_ptr);
+    if (e != hipSuccess || attr.type != hipMemoryTypeHost) {
+        (void)hipGetLastError();  // a failed query leaves its error behind
+        return fail(RV_ERR_INVALID_ARG, "%p is not pinned host memory (hipHostMalloc)", host_ptr);
+    }
+    void *d = nullptr;
+    e = hipHostGetDevicePointer(&d, const_cast<void *>(host_ptr), 0);
+    if (e != hipSuccess || d == nullptr) {
+        (void)hipGetLastError();
+        return fail(RV_ERR_INVALID_ARG, "no device mapping of %p: %s", host_ptr,
+                    hipGetErrorString(e));
+    }
+    *device_ptr = d;
+    return RV_OK;
+}
+
 int rv_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
                      void *stream) {
     g_error[0] = '\0';

@@ -67,6 +67,19 @@ def test_noalloc_scratch_limit(lib):
     assert "allocation-free" in lib.rv_last_error().decode()
 
 
+def test_host_device_pointer_refuses_unmapped_memory(lib):
+    # NULL and pageable memory are refused on the host (-1) and leave *device NULL
+    import numpy as np
+
+    d = ctypes.c_void_p(1234)
+    assert lib.rv_host_device_pointer(None, ctypes.byref(d)) == -1 and d.value is None
+    a = np.zeros(16, np.float32)
+    d = ctypes.c_void_p(1234)
+    assert lib.rv_host_device_pointer(ctypes.c_void_p(a.ctypes.data), ctypes.byref(d)) == -1
+    assert d.value is None
+    assert lib.rv_host_device_pointer(ctypes.c_void_p(a.ctypes.data), None) == -1
+
+
 def test_workspace_bytes(lib):
     from paper_2012_12618_amd import binding
 
