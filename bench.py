@@ -247,7 +247,7 @@ def sum_evals(frame, n_hyp):
 
 
 def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_frames,
-                zero_copy=False):
+                zero_copy=False, pipelined_parts=()):
     """Host-clock latency of n_frames distinct frames, each from pinned host
     memory through the H2D copies, the estimate and the D2H copies of the
     per-cluster results (synchronised per frame).  Frame i is drawn fresh for
@@ -256,12 +256,14 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
     draws) with every azimuth turned by a distinct angle of at most 0.062 rad,
     so that no two timed frames are equal.  Each frame is written into the
     pinned buffer before its clock starts.  Returns (milliseconds per frame,
-    recipe text, and with zero_copy the milliseconds per frame of the same frames
-    estimated straight from and into pinned host memory, else None)."""
+    recipe text, with zero_copy the milliseconds per frame of the same frames
+    estimated straight from and into pinned host memory, else None, and for each
+    count P of pipelined_parts the milliseconds per frame of the same frames sent
+    and estimated in P parts, a part's estimate overlapping the next part's copy)."""
     import numpy as np
 
     if n_frames <= 0:
-        return [], None, None
+        return [], None, None, {}
     spec = synth.WORKLOADS[name][0]
     if name == "small":
         bases = [synth.make_frame(spec, 100_000 + i) for i in range(n_frames)]
@@ -312,8 +314,11 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
     for i in range(min(8, n_frames)):  # untimed first use of the buffers
         one(i, synth.ransac_seed(name, 9_000 + i))
     lat = [one(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    pipe = {P: pipelined_latency(torch, binding, dev, stream, frame_at, n_frames, n_hyp, tau, P,
+                                 (h_t, h_v, d_t, d_v), res, name, synth)
+            for P in pipelined_parts}
     if not zero_copy:
-        return lat, recipe, None
+        return lat, recipe, None, pipe
 
     # The same frames with no copies: inputs and outputs in pinned host memory,
     # read and written by the kernels through their device mapping, one
@@ -338,7 +343,61 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
     for i in range(min(8, n_frames)):
         zero(i, synth.ransac_seed(name, 9_000 + i))
     lat_z = [zero(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
-    return lat, recipe, lat_z
+    return lat, recipe, lat_z, pipe
+
+
+def pipelined_latency(torch, binding, dev, stream, frame_at, n_frames, n_hyp, tau, n_parts,
+                      buffers, res, name, synth):
+    """Host-clock latency of the frames of latency_run sent and estimated in
+    n_parts parts of about equal points by rv_estimate_velocity_pipelined: part
+    j's estimate runs on the compute stream while part j + 1 is copied on a copy
+    stream, and the per-cluster results are written straight into pinned host
+    memory through its device mapping.  The clock covers the call (cutting the
+    frame, every enqueue) and the final synchronisation.  Also checks the first
+    frame's results against the whole-frame call bit for bit.  Returns
+    (milliseconds per frame, whether the results matched)."""
+    import numpy as np
+
+    h_t, h_v, d_t, d_v = buffers
+    k_max = max(res["vx"].shape[0], 1)
+    copy_stream = torch.cuda.Stream(device=dev)
+    h_o = torch.empty(k_max + 1, dtype=torch.int32).pin_memory()
+    d_o = torch.empty(k_max + 1, dtype=torch.int32, device=dev)
+    keys = ("vx", "vy", "heading", "n_inliers", "status")
+    z = {k: torch.empty(res[k].shape, dtype=res[k].dtype).pin_memory() for k in keys}
+    z["workspace"] = torch.empty(max(binding.rv_workspace_bytes(k_max, h_t.shape[0], n_hyp), 1),
+                                 dtype=torch.uint8, device=dev)
+
+    def run(i, seed):
+        th, vd, off = frame_at(i)
+        n, k = th.shape[0], off.shape[0] - 1
+        h_t[:n].numpy()[:] = th
+        h_v[:n].numpy()[:] = vd
+        h_o[:k + 1].numpy()[:] = off
+        part_out = {key: v[:k] for key, v in z.items() if key != "workspace"}
+        part_out["workspace"] = z["workspace"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binding.rv_estimate_velocity_pipelined(h_t[:n], h_v[:n], h_o[:k + 1], n_parts, n_hyp, tau,
+                                               seed, device_inputs=(d_t, d_v, d_o), out=part_out,
+                                               stream=stream, copy_stream=copy_stream)
+        stream.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    seed0 = synth.ransac_seed(name, 9_000)
+    run(0, seed0)
+    th, vd, off = frame_at(0)
+    whole = binding.rv_estimate_velocity(torch.from_numpy(th).to(dev), torch.from_numpy(vd).to(dev),
+                                         torch.from_numpy(off).to(dev), n_hyp, tau, seed0,
+                                         want_near=False, stream=stream)
+    stream.synchronize()
+    k0 = off.shape[0] - 1
+    same = all(np.array_equal(z[key][:k0].numpy().view(np.uint8),
+                              whole[key].cpu().numpy().view(np.uint8)) for key in keys)
+    for i in range(1, min(8, n_frames)):
+        run(i, synth.ransac_seed(name, 9_000 + i))
+    lat = [run(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    return lat, same
 
 
 def batch_bench(args, torch, binding, synth, dev) -> dict:
@@ -974,8 +1033,10 @@ def frame_bench(args, torch, binding, synth, dev, name) -> dict:
     print(f"[bench] latency over {args.latency_frames} distinct frames", file=sys.stderr, flush=True)
     # Small frames also straight from and into pinned host memory (no copies);
     # a large frame would send its seed-azimuth reads over PCIe, so it is copied.
-    lat, lat_recipe, lat_z = latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp,
-                                         tau, args.latency_frames, zero_copy=small_path)
+    # Large frames are also sent in parts, each part's estimate overlapping the next one's copy.
+    lat, lat_recipe, lat_z, lat_p = latency_run(
+        torch, binding, synth, dev, stream, name, frame, n_hyp, tau, args.latency_frames,
+        zero_copy=small_path, pipelined_parts=() if small_path else (2, 4, 8))
 
     calibration_copy(torch, dev, args.copy_calibration_mb)
 
@@ -1041,6 +1102,14 @@ def frame_bench(args, torch, binding, synth, dev, name) -> dict:
                                            "writing the per-cluster results in pinned host memory "
                                            "through their device mapping (no copies)"}
                                  if lat_z else None),
+        "latency_pipelined_ms": ({
+            "parts": {str(P): {"p50": percentile(v[0], 50), "p99": percentile(v[0], 99),
+                               "bitwise_equal_to_whole_frame": v[1]} for P, v in lat_p.items()},
+            "frames": len(lat), "frames_recipe": lat_recipe,
+            "scope": "pinned host frame -> rv_estimate_velocity_pipelined: P parts cut at "
+                     "cluster boundaries, the H2D copy of part j+1 on a copy stream overlapping "
+                     "the estimate of part j -> per-cluster results written into pinned host "
+                     "memory through its device mapping"} if lat_p else None),
         "step_ms": {"median": percentile(step_times, 50), "p99": percentile(step_times, 99),
                     "scope": "single steps, a second pass with an event between steps"},
         "stage_ms": dict(zip(binding.STAGE_NAMES, stage_avg)),

@@ -118,6 +118,79 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
                          size_t workspace_bytes, void *stream);
 
 /*
+ * ---- Part of a frame -----------------------------------------------------------
+ *
+ * rv_estimate_velocity_part estimates clusters [first_cluster, first_cluster +
+ * n_clusters) of a larger frame, so that a frame can be sent to the GPU and
+ * estimated in pieces (the estimate of one piece overlapping the copy of the
+ * next).  Each cluster draws its hypotheses with the counter of its index in
+ * the whole frame, (h, first_cluster + k, 0, 0) for the part's k-th cluster
+ * (Sec. 3.1: seed pairs drawn per cluster), so every per-cluster output is bit
+ * for bit what rv_estimate_velocity gives for the whole frame.
+ *   - theta and vd hold the part's n_points points: the whole frame's arrays
+ *     from point first_point on.  cluster_offsets[n_clusters + 1] are the
+ *     whole frame's offsets of the part's clusters (the whole frame's array
+ *     from entry first_cluster on), so cluster k of the part owns the part's
+ *     points [offsets[k] - first_point, offsets[k+1] - first_point); a cluster
+ *     outside [0, n_points) of the part gets RV_CLUSTER_BAD_OFFSETS.
+ *   - Outputs are indexed by the part's cluster k (the whole frame's outputs
+ *     from entry first_cluster on, hyp_counts from first_cluster * n_hyp).
+ *     inlier_bits covers the part's points, bit p of the part's point p, and
+ *     ceil(n_points/32) words of it are cleared: a frame-wide mask can be
+ *     shared by parts whose first points are multiples of 32, each given the
+ *     word of its first point.
+ *   - first_cluster in [0, 2^32 - 1] with first_cluster + n_clusters <= 2^32
+ *     (the counter is 32 bits), first_point in [0, 2^31 - 1]; else
+ *     RV_ERR_INVALID_ARG.
+ *   - Workspace: rv_workspace_bytes(n_clusters, n_points, n_hyp) of the part.
+ *     Parts ordered on one stream may share one workspace.
+ * first_cluster = first_point = 0 with the whole frame is rv_estimate_velocity.
+ */
+int rv_estimate_velocity_part(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                              int64_t n_clusters, int64_t n_points, int64_t first_cluster,
+                              int64_t first_point, int32_t n_hyp, float tau, uint64_t seed,
+                              float *vx, float *vy, float *heading, int32_t *n_inliers,
+                              uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                              int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                              size_t workspace_bytes, void *stream);
+
+/*
+ * rv_estimate_velocity_pipelined: one frame from host memory, copied to the
+ * GPU and estimated in n_parts parts of about equal points (cut at cluster
+ * boundaries), part j's estimate (rv_estimate_velocity_part) running on
+ * `stream` while part j + 1 is copied on `copy_stream`.  The outputs are bit
+ * for bit those of rv_estimate_velocity on the whole frame.
+ *   theta_host, vd_host [n_points], offsets_host [n_clusters + 1]: host memory,
+ *     pinned (hipHostMalloc, torch's pin_memory()) for the copies to run
+ *     asynchronously.  The host reads offsets_host during the call to cut the
+ *     frame and size the copies: it must start at 0, not decrease and end at
+ *     n_points (else RV_ERR_INVALID_ARG, nothing enqueued).  The caller keeps
+ *     the host arrays unchanged until `stream` has finished the call's work.
+ *   theta_dev, vd_dev [n_points], offsets_dev [n_clusters + 1]: device memory
+ *     the call copies the frame into (the caller's; contents overwritten).
+ *   Outputs as rv_estimate_velocity (device memory, or pinned host memory
+ *     through rv_host_device_pointer), without the frame-wide inlier mask
+ *     (parts cut at cluster boundaries need not start on 32-point words: use
+ *     rv_estimate_velocity or rv_estimate_velocity_part for the mask).
+ *   n_parts in [1, RV_MAX_PARTS]; workspace as rv_estimate_velocity.
+ *   copy_stream: a stream of the same device other than `stream` (the same
+ *     stream is correct but overlaps nothing).  Its copies are ordered after
+ *     the work already queued on it; the call makes `stream` wait for them.
+ * The call returns once everything is enqueued; the results are ready when
+ * `stream` is.
+ */
+#define RV_MAX_PARTS 64
+
+int rv_estimate_velocity_pipelined(const float *theta_host, const float *vd_host,
+                                   const int32_t *offsets_host, int64_t n_clusters,
+                                   int64_t n_points, int32_t n_parts, int32_t n_hyp, float tau,
+                                   uint64_t seed, float *theta_dev, float *vd_dev,
+                                   int32_t *offsets_dev, float *vx, float *vy, float *heading,
+                                   int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
+                                   int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                                   size_t workspace_bytes, void *stream, void *copy_stream);
+
+/*
  * ---- Allocation-free form ----------------------------------------------------
  *
  * For callers that cannot allocate device memory around the estimate: code

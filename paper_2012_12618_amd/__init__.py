@@ -16,7 +16,9 @@ _BINDING_NAMES = (
     "rv_tuning_default", "rv_batch_workspace_bytes", "rv_estimate_velocity_batch",
     "rv_graph_capture_batch", "allocate_batch_outputs", "RVTuning", "RVGraph",
     "RVServer", "RVServerConfig", "rv_server_config_default", "rv_server_frame_bytes",
-    "rv_estimate_velocity_paper", "rv_paper_workspace_bytes",
+    "rv_estimate_velocity_paper", "rv_paper_workspace_bytes", "rv_estimate_velocity_part",
+    "rv_estimate_velocity_pipelined", "rv_estimate_velocity_noalloc",
+    "host_device_pointer", "PreparedEstimate",
 )
 
 __all__ = list(_BINDING_NAMES)

@@ -33,6 +33,7 @@ RV_MIN_SEED_SEPARATION = 1e-3
 RV_NEAR_TAU_WINDOW = 1e-5
 RV_MAX_HYP = 1 << 20
 RV_NOALLOC_SCRATCH_BYTES = 96 << 20
+RV_MAX_PARTS = 64
 
 RV_TUNE_BUCKETS = 8
 
@@ -119,6 +120,16 @@ def load_library() -> ctypes.CDLL:
     lib.rv_estimate_velocity.argtypes = [
         P, P, P, i64, i64, i32, ctypes.c_float, ctypes.c_uint64,
         P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P,
+    ]
+    lib.rv_estimate_velocity_part.restype = ctypes.c_int
+    lib.rv_estimate_velocity_part.argtypes = [
+        P, P, P, i64, i64, i64, i64, i32, ctypes.c_float, ctypes.c_uint64,
+        P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P,
+    ]
+    lib.rv_estimate_velocity_pipelined.restype = ctypes.c_int
+    lib.rv_estimate_velocity_pipelined.argtypes = [
+        P, P, P, i64, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, P, P, P,
+        P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P, P,
     ]
     lib.rv_estimate_velocity_noalloc.restype = ctypes.c_int
     lib.rv_estimate_velocity_noalloc.argtypes = [
@@ -301,6 +312,30 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     n_inliers, status and, when requested, n_near_tau, inlier_bits (int32 words,
     bit p%32 of word p/32 is point p), hyp_counts [K*H], best_hyp.
     """
+    return _estimate(theta, vd, offsets, None, n_hyp, tau, seed, want_near, want_bits, debug,
+                     out, stream, validate)
+
+
+def rv_estimate_velocity_part(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
+                              first_cluster: int, first_point: int, n_hyp: int, tau: float,
+                              seed: int, *, want_near: bool = True, want_bits: bool = False,
+                              debug: bool = False, out: dict | None = None,
+                              stream: torch.cuda.Stream | None = None) -> dict:
+    """rv_estimate_velocity for a part of a larger frame: its clusters are the
+    frame's clusters ``first_cluster ..``, and each draws its hypotheses with its
+    index in the whole frame, so the outputs are bit for bit the whole frame's.
+    ``theta`` and ``vd`` are the part's points (the frame's from ``first_point``
+    on); ``offsets`` are the frame's offsets of the part's clusters (frame point
+    indexes).  Other arguments and the results are those of
+    rv_estimate_velocity, indexed by the part's clusters and points."""
+    return _estimate(theta, vd, offsets, (int(first_cluster), int(first_point)), n_hyp, tau, seed,
+                     want_near, want_bits, debug, out, stream, False)
+
+
+def _estimate(theta, vd, offsets, part, n_hyp, tau, seed, want_near, want_bits, debug,
+              out, stream, validate) -> dict:
+    """The whole-frame entry point when ``part`` is None, else the part one
+    with part = (first_cluster, first_point)."""
     lib = load_library()
     device = _call_device(theta)
     n_points = int(theta.numel())
@@ -320,18 +355,84 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     ws = out["workspace"]
     if stream is None:
         stream = torch.cuda.current_stream(device)
-    code = lib.rv_estimate_velocity(
+    inputs = (
         _dev_ptr(theta, torch.float32, device, "theta", host_ok=True),
         _dev_ptr(vd, torch.float32, device, "vd", host_ok=True),
         _dev_ptr(offsets, torch.int32, device, "offsets", host_ok=True),
-        n_clusters, n_points, int(n_hyp), float(tau), int(seed) & 0xFFFFFFFFFFFFFFFF,
+        n_clusters, n_points)
+    rest = (
+        int(n_hyp), float(tau), int(seed) & 0xFFFFFFFFFFFFFFFF,
         *_output_ptrs(out, device, n_clusters, n_points, n_hyp, host_ok=True),
         _dev_ptr(ws, torch.uint8, device, "workspace"), int(ws.numel()),
-        ctypes.c_void_p(stream.cuda_stream),
-    )
+        ctypes.c_void_p(stream.cuda_stream))
+    if part is None:
+        code = lib.rv_estimate_velocity(*inputs, *rest)
+    else:
+        code = lib.rv_estimate_velocity_part(*inputs, *part, *rest)
     _check(code)
     if owned:
         _used_on(stream, out.values())
+    return {k: v for k, v in out.items() if k != "workspace"}
+
+
+def rv_estimate_velocity_pipelined(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
+                                   n_parts: int, n_hyp: int, tau: float, seed: int, *,
+                                   device_inputs: tuple | None = None, want_near: bool = True,
+                                   debug: bool = False, out: dict | None = None,
+                                   stream: torch.cuda.Stream | None = None,
+                                   copy_stream: torch.cuda.Stream | None = None) -> dict:
+    """One frame from host memory, copied and estimated in ``n_parts`` parts
+    (rv_estimate_velocity_pipelined): each part's estimate on ``stream``
+    overlaps the next part's copy on ``copy_stream`` (default: a new stream).
+    ``theta``/``vd``/``offsets``: contiguous CPU tensors, pinned for the copies
+    to overlap; ``device_inputs``: (theta, vd, offsets) device tensors of at
+    least the frame's sizes that receive the copies (allocated if None).  The
+    results (no inlier mask) are those of rv_estimate_velocity on the whole
+    frame; ``out`` may hold device or pinned host tensors.  The host tensors
+    must stay unchanged until ``stream`` has finished."""
+    lib = load_library()
+    for name, t in (("theta", theta), ("vd", vd), ("offsets", offsets)):
+        if t.device.type != "cpu" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous host tensor")
+    if theta.dtype != torch.float32 or vd.dtype != torch.float32 or offsets.dtype != torch.int32:
+        raise TypeError("theta and vd must be float32, offsets int32")
+    device = torch.device("cuda", torch.cuda.current_device())
+    n_points = int(theta.numel())
+    n_clusters = int(offsets.numel()) - 1
+    if n_clusters < 0 or int(vd.numel()) != n_points:
+        raise ValueError("offsets needs n_clusters + 1 entries; theta and vd must match")
+    if device_inputs is None:
+        device_inputs = (torch.empty(n_points, dtype=torch.float32, device=device),
+                         torch.empty(n_points, dtype=torch.float32, device=device),
+                         torch.empty(n_clusters + 1, dtype=torch.int32, device=device))
+    d_t, d_v, d_o = device_inputs
+    owned = out is None
+    if out is None:
+        out = allocate_outputs(n_clusters, n_points, n_hyp, device, want_near=want_near,
+                               want_bits=False, debug=debug)
+    if out.get("inlier_bits") is not None:
+        raise ValueError("the pipelined form gives no inlier mask")
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    if copy_stream is None:
+        copy_stream = torch.cuda.Stream(device=device)
+    ws = out["workspace"]
+    ptrs = _output_ptrs(out, device, n_clusters, n_points, n_hyp, host_ok=True)
+    code = lib.rv_estimate_velocity_pipelined(
+        ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(vd.data_ptr()),
+        ctypes.c_void_p(offsets.data_ptr()), n_clusters, n_points, int(n_parts), int(n_hyp),
+        float(tau), int(seed) & 0xFFFFFFFFFFFFFFFF,
+        _dev_ptr(d_t, torch.float32, device, "theta (device)", n_points),
+        _dev_ptr(d_v, torch.float32, device, "vd (device)", n_points),
+        _dev_ptr(d_o, torch.int32, device, "offsets (device)", n_clusters + 1),
+        *ptrs[:6], *ptrs[7:],
+        _dev_ptr(ws, torch.uint8, device, "workspace"), int(ws.numel()),
+        ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(copy_stream.cuda_stream))
+    _check(code)
+    if owned:
+        _used_on(stream, out.values())
+    _used_on(stream, device_inputs)
+    _used_on(copy_stream, device_inputs)
     return {k: v for k, v in out.items() if k != "workspace"}
 
 

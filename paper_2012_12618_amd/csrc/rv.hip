@@ -214,7 +214,7 @@ __device__ __forceinline__ void plan_scan(const uint32_t *count, uint32_t *start
     }
 }
 
-__device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
+__device__ void plan_order(const int32_t *__restrict__ off, int64_t point_base, int64_t n_clusters,
                            int64_t n_points, int32_t *__restrict__ order,
                            int64_t *__restrict__ n_big) {
     __shared__ uint32_t count[kSizeClasses];
@@ -230,7 +230,7 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
 #pragma unroll
         for (int u = 0; u < kPlanUnroll; ++u) {
             const int64_t k = threadIdx.x + (int64_t)u * kPrepBlock;
-            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
+            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points, point_base).n) : -1;
         }
 #pragma unroll
         for (int u = 0; u < kPlanUnroll; ++u)
@@ -252,7 +252,7 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
 #pragma unroll
         for (int u = 0; u < kPlanUnroll; ++u) {
             const int64_t k = k0 + (int64_t)u * kPrepBlock;
-            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
+            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points, point_base).n) : -1;
         }
 #pragma unroll
         for (int u = 0; u < kPlanUnroll; ++u)
@@ -266,7 +266,7 @@ __device__ void plan_order(const int32_t *__restrict__ off, int64_t n_clusters,
 #pragma unroll
         for (int u = 0; u < kPlanUnroll; ++u) {
             const int64_t k = k0 + (int64_t)u * kPrepBlock;
-            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points).n) : -1;
+            cls[u] = k < n_clusters ? size_class(cluster_span(off, k, n_points, point_base).n) : -1;
         }
 #pragma unroll
         for (int u = 0; u < kPlanUnroll; ++u) {
@@ -304,11 +304,11 @@ __global__ __launch_bounds__(kPrepBlock) void prep_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd, int64_t n_points,
     float2 *__restrict__ cs32, float *__restrict__ v32, float2 *__restrict__ cslo,
     uint32_t *__restrict__ bits,
-    int64_t n_words, const int32_t *__restrict__ off, int64_t n_clusters,
+    int64_t n_words, const int32_t *__restrict__ off, int64_t point_base, int64_t n_clusters,
     int32_t *__restrict__ order, int64_t *__restrict__ n_big,
     unsigned long long *__restrict__ best_key) {
     if (blockIdx.x == 0) {
-        if (order != nullptr) plan_order(off, n_clusters, n_points, order, n_big);
+        if (order != nullptr) plan_order(off, point_base, n_clusters, n_points, order, n_big);
         return;
     }
     const int64_t p = (int64_t)(blockIdx.x - 1) * kPrepBlock + threadIdx.x;
@@ -1229,8 +1229,8 @@ __device__ __forceinline__ void refit_wave(Span sp, ClusterId id, unsigned long 
 __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))) void score_kernel(
     const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
     int64_t n_points, int32_t n_hyp, int32_t blocks_per_cluster, uint32_t key0, uint32_t key1,
-    Points pts, float tau, unsigned long long *__restrict__ best_key,
-    int32_t *__restrict__ hyp_counts) {
+    uint32_t cluster_base, int64_t point_base, Points pts, float tau,
+    unsigned long long *__restrict__ best_key, int32_t *__restrict__ hyp_counts) {
     __shared__ float4 s_hyp[kScoreBlock / 2];  // (vx, vy) pairs, two per float4
     __shared__ unsigned long long s_key[kScoreBlock / kWave];
     __shared__ LaneShared s_lanes;
@@ -1243,10 +1243,10 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     const int64_t k = order != nullptr ? order[j] : j;
     ClusterId id;
     id.out = k;
-    id.local = (uint32_t)k;
+    id.local = cluster_base + (uint32_t)k;
     id.key0 = key0;
     id.key1 = key1;
-    const Span sp = cluster_span(off, k, n_points);
+    const Span sp = cluster_span(off, k, n_points, point_base);
     if (sp.ok && sp.n >= 2 && sp.n <= kSingleLanesMax) {  // the same for the whole block
         score_block_lanes(sp, id, b, n_hyp, pts, tau, s_lanes, best_key, hyp_counts);
         return;
@@ -1283,15 +1283,18 @@ __device__ __forceinline__ void refit_planned(int64_t n_clusters, const int64_t 
 struct FrameClusterAt {
     const int32_t *off, *order;
     int64_t n_points;
-    uint32_t key0, key1;
+    uint32_t key0, key1, cluster_base;
+    int64_t point_base;
     const unsigned long long *best_key;
     __device__ int64_t index(int64_t j) const { return order != nullptr ? order[j] : j; }
-    __device__ Span span(int64_t j) const { return cluster_span(off, index(j), n_points); }
+    __device__ Span span(int64_t j) const {
+        return cluster_span(off, index(j), n_points, point_base);
+    }
     __device__ unsigned long long best(int64_t j) const { return best_key[index(j)]; }
     __device__ ClusterId id(int64_t j) const {
         ClusterId c;
         c.out = index(j);
-        c.local = (uint32_t)c.out;
+        c.local = cluster_base + (uint32_t)c.out;
         c.key0 = key0;
         c.key1 = key1;
         return c;
@@ -1300,11 +1303,13 @@ struct FrameClusterAt {
 
 __global__ __launch_bounds__(kRefitBlock) void refit_kernel(
     const int32_t *__restrict__ off, const int32_t *__restrict__ order, int64_t n_clusters,
-    const int64_t *__restrict__ n_big, int64_t n_points, uint32_t key0, uint32_t key1, Points pts,
+    const int64_t *__restrict__ n_big, int64_t n_points, uint32_t key0, uint32_t key1,
+    uint32_t cluster_base, int64_t point_base, Points pts,
     const unsigned long long *__restrict__ best_key, float tau, Outputs o) {
     __shared__ double s_sum[kRefitBlock / kWave][5];
     __shared__ int s_cnt[kRefitBlock / kWave][2];
-    const FrameClusterAt at = {off, order, n_points, key0, key1, best_key};
+    const FrameClusterAt at = {off, order, n_points, key0, key1, cluster_base, point_base,
+                               best_key};
     refit_planned(n_clusters, n_big, at, pts, tau, o, s_sum, s_cnt);
 }
 
@@ -1330,7 +1335,8 @@ __global__ __launch_bounds__(kRefitBlock) void refit_kernel(
 // compute unit's L1, which its own stores keep current).
 __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))) void small_frame_kernel(
     const float *__restrict__ theta, const float *__restrict__ vd, const int32_t *__restrict__ off,
-    int64_t n_points, int32_t n_hyp, uint32_t key0, uint32_t key1, Points pts, float tau,
+    int64_t n_points, int32_t n_hyp, uint32_t key0, uint32_t key1, uint32_t cluster_base,
+    int64_t point_base, Points pts, float tau,
     float2 *__restrict__ cs32, float *__restrict__ v32, float2 *__restrict__ cslo,
     unsigned long long *__restrict__ best_key, Outputs o) {
     __shared__ float4 s_hyp[kScoreBlock / 2];
@@ -1340,14 +1346,14 @@ __global__ __launch_bounds__(kScoreBlock) __attribute__((amdgpu_waves_per_eu(8))
     __shared__ LaneShared s_lanes;
     __shared__ TailShared s_tail;
     const int64_t k = blockIdx.x;
-    const Span sp = cluster_span(off, k, n_points);
+    const Span sp = cluster_span(off, k, n_points, point_base);
     for (int64_t p = sp.lo + threadIdx.x; p < sp.lo + sp.n; p += kScoreBlock)
         stage_point(theta, vd, p, cs32, v32, cslo);
     if (threadIdx.x == 0) best_key[k] = 0;
     __syncthreads();
     ClusterId id;
     id.out = k;
-    id.local = (uint32_t)k;
+    id.local = cluster_base + (uint32_t)k;
     id.key0 = key0;
     id.key1 = key1;
     // The workgroup's own block key is the cluster's best (one block per
@@ -1749,14 +1755,16 @@ int device_cus() {
 // ordering pass's count of big clusters.
 void launch_refit(bool batch, const int32_t *off, const int32_t *order, const ItemDesc *desc,
                   int64_t n_clusters, const int64_t *n_big, int64_t n_points, uint32_t key0,
-                  uint32_t key1, const Points &pts, const unsigned long long *best_key, float tau,
-                  const Outputs &o, hipStream_t st) {
+                  uint32_t key1, uint32_t cluster_base, int64_t point_base, const Points &pts,
+                  const unsigned long long *best_key, float tau, const Outputs &o,
+                  hipStream_t st) {
     if (batch)
         hipLaunchKernelGGL(batch_refit_kernel, dim3((unsigned)n_clusters), dim3(kRefitBlock), 0, st,
                            desc, n_clusters, n_big, pts, best_key, tau, o);
     else
         hipLaunchKernelGGL(refit_kernel, dim3((unsigned)n_clusters), dim3(kRefitBlock), 0, st, off,
-                           order, n_clusters, n_big, n_points, key0, key1, pts, best_key, tau, o);
+                           order, n_clusters, n_big, n_points, key0, key1, cluster_base,
+                           point_base, pts, best_key, tau, o);
 }
 
 // Persistent grid of the batched scoring kernel on the current device.
@@ -1830,7 +1838,7 @@ int launch_batch(const BatchArgs &a, unsigned grid, hipStream_t st, bool allow_t
                            queues, best_key, a.o.hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
     launch_refit(true, nullptr, nullptr, (const ItemDesc *)desc, a.n_clusters, n_big, a.n_points,
-                 0, 0, pts, best_key, a.tau, a.o, st);
+                 0, 0, 0, 0, pts, best_key, a.tau, a.o, st);
     if (timed) {
         (void)hipEventRecord(tc.ev[3], st);
         keep_timed_call(tc);
@@ -1898,8 +1906,10 @@ int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_o
                    float *vx, float *vy, float *heading, int32_t *n_inliers, uint8_t *status,
                    int32_t *n_near_tau, uint32_t *inlier_bits, int32_t *hyp_counts,
                    int32_t *best_hyp, void *workspace, size_t workspace_bytes, void *stream,
-                   bool allow_timing) {
+                   uint32_t first_cluster, int64_t first_point, bool allow_timing) {
     if (n_clusters < 0) return fail(RV_ERR_INVALID_ARG, "n_clusters < 0");
+    if ((uint64_t)first_cluster + (uint64_t)n_clusters > ((uint64_t)1 << 32))
+        return fail(RV_ERR_INVALID_ARG, "first_cluster + n_clusters exceeds 2^32");
     if (n_points < 0 || n_points > INT32_MAX)
         return fail(RV_ERR_INVALID_ARG, "n_points must be in [0, 2^31 - 1]");
     if (n_hyp < 1 || n_hyp > RV_MAX_HYP)
@@ -1959,8 +1969,8 @@ int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_o
         // One launch; its time counts as the scoring stage.
         if (timed) (void)hipEventRecord(tc.ev[1], st);
         hipLaunchKernelGGL(small_frame_kernel, dim3((unsigned)n_clusters), dim3(kScoreBlock), 0, st,
-                           theta, vd, cluster_offsets, n_points, n_hyp, key0, key1, pts, tau, cs32,
-                           v32, cslo, best_key, o);
+                           theta, vd, cluster_offsets, n_points, n_hyp, key0, key1, first_cluster,
+                           first_point, pts, tau, cs32, v32, cslo, best_key, o);
         if (timed) {
             (void)hipEventRecord(tc.ev[2], st);
             (void)hipEventRecord(tc.ev[3], st);
@@ -1975,16 +1985,16 @@ int estimate_frame(const float *theta, const float *vd, const int32_t *cluster_o
     const int64_t prep_blocks = (prep_items + kPrepBlock - 1) / kPrepBlock + 1;  // + planner
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)prep_blocks), dim3(kPrepBlock), 0, st, theta,
                        vd, n_points, cs32, v32, cslo, inlier_bits, n_words, cluster_offsets,
-                       n_clusters, order, n_big, best_key);
+                       first_point, n_clusters, order, n_big, best_key);
     if (timed) (void)hipEventRecord(tc.ev[1], st);
     hipLaunchKernelGGL(score_kernel, dim3((unsigned)(clusters_xcd * blocks_per_cluster)),
                        dim3(kScoreBlock), 0, st, cluster_offsets, (const int32_t *)order,
                        n_clusters, n_points, n_hyp, (int32_t)blocks_per_cluster, key0, key1,
-                       pts, tau, best_key, hyp_counts);
+                       first_cluster, first_point, pts, tau, best_key, hyp_counts);
     if (timed) (void)hipEventRecord(tc.ev[2], st);
     launch_refit(false, cluster_offsets, order, nullptr, n_clusters,
-                 order != nullptr ? (const int64_t *)n_big : nullptr, n_points, key0, key1, pts,
-                 best_key, tau, o, st);
+                 order != nullptr ? (const int64_t *)n_big : nullptr, n_points, key0, key1,
+                 first_cluster, first_point, pts, best_key, tau, o, st);
     if (timed) {
         (void)hipEventRecord(tc.ev[3], st);
         keep_timed_call(tc);
@@ -2040,6 +2050,126 @@ int device_scratch(hipStream_t stream, void **ptr) {
     return RV_OK;
 }
 
+// ---- A frame sent and estimated in parts ---------------------------------------
+// Events that order a part's estimate after its copy, kept per device and
+// reused: a wait enqueued on a stream holds on to the record that precedes it,
+// so an event may go back to the pool as soon as its wait is enqueued.
+std::mutex g_event_mutex;
+std::vector<hipEvent_t> g_events[kMaxDevices];
+
+int take_events(int dev, int n, hipEvent_t *ev) {
+    std::lock_guard<std::mutex> lock(g_event_mutex);
+    std::vector<hipEvent_t> &pool = g_events[dev];
+    for (int i = 0; i < n; ++i) {
+        if (pool.empty()) {
+            const hipError_t e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+            if (e != hipSuccess) {
+                for (int j = 0; j < i; ++j) pool.push_back(ev[j]);
+                return fail(RV_ERR_HIP, "hipEventCreateWithFlags failed: %s",
+                            hipGetErrorString(e));
+            }
+        } else {
+            ev[i] = pool.back();
+            pool.pop_back();
+        }
+    }
+    return RV_OK;
+}
+
+void give_events(int dev, int n, const hipEvent_t *ev) {
+    std::lock_guard<std::mutex> lock(g_event_mutex);
+    for (int i = 0; i < n; ++i) g_events[dev].push_back(ev[i]);
+}
+
+// Clusters [cut[j], cut[j+1]) form part j: the first cluster whose end reaches
+// j/n_parts of the points starts a new part (empty parts are dropped).  Returns
+// the number of parts.
+int cut_parts(const int32_t *off, int64_t n_clusters, int64_t n_points, int n_parts,
+              int64_t *cut) {
+    int m = 0;
+    cut[m++] = 0;
+    int64_t k = 0;
+    for (int j = 1; j < n_parts; ++j) {
+        const int64_t target = n_points * j / n_parts;
+        while (k < n_clusters && off[k] < target) ++k;
+        if (k > cut[m - 1] && k < n_clusters) cut[m++] = k;
+    }
+    cut[m++] = n_clusters;  // n_clusters > 0: every cut above is below it
+    return m - 1;
+}
+
+int estimate_pipelined(const float *theta_host, const float *vd_host,
+                       const int32_t *offsets_host, int64_t n_clusters, int64_t n_points,
+                       int32_t n_parts, int32_t n_hyp, float tau, uint64_t seed, float *theta_dev,
+                       float *vd_dev, int32_t *offsets_dev, float *vx, float *vy, float *heading,
+                       int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
+                       int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                       size_t workspace_bytes, hipStream_t st, hipStream_t copy_st) {
+    if (n_clusters < 0 || n_points < 0 || n_points > INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "sizes out of range");
+    if (n_parts < 1 || n_parts > RV_MAX_PARTS)
+        return fail(RV_ERR_INVALID_ARG, "n_parts must be in [1, %d]", RV_MAX_PARTS);
+    if (offsets_host == nullptr || offsets_dev == nullptr)
+        return fail(RV_ERR_INVALID_ARG, "offsets pointers are NULL");
+    if (n_points > 0 && (theta_host == nullptr || vd_host == nullptr || theta_dev == nullptr ||
+                         vd_dev == nullptr))
+        return fail(RV_ERR_INVALID_ARG, "theta or vd pointers are NULL");
+    // The host reads the offsets to cut the frame and to size the copies, so
+    // they must describe the frame exactly.
+    if (offsets_host[0] != 0 || offsets_host[n_clusters] != n_points)
+        return fail(RV_ERR_INVALID_ARG, "offsets must start at 0 and end at n_points");
+    for (int64_t k = 0; k < n_clusters; ++k)
+        if (offsets_host[k + 1] < offsets_host[k])
+            return fail(RV_ERR_INVALID_ARG, "offsets decrease at cluster %lld", (long long)k);
+    if (n_clusters == 0) return RV_OK;
+    if (workspace_bytes < rv_workspace_bytes(n_clusters, n_points, n_hyp))
+        return fail(RV_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", workspace_bytes,
+                    rv_workspace_bytes(n_clusters, n_points, n_hyp));
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(RV_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(RV_ERR_HIP, "device index %d outside [0, %d)", dev, kMaxDevices);
+    int64_t cut[RV_MAX_PARTS + 1];
+    const int m = cut_parts(offsets_host, n_clusters, n_points, n_parts, cut);
+    hipEvent_t ev[RV_MAX_PARTS];
+    int rc = take_events(dev, m, ev);
+    if (rc != RV_OK) return rc;
+    // Every copy first, so that the copy engine never waits for the host; then
+    // each part's estimate behind its copy.
+    e = hipMemcpyAsync(offsets_dev, offsets_host, (size_t)(n_clusters + 1) * sizeof(int32_t),
+                       hipMemcpyHostToDevice, copy_st);
+    for (int j = 0; j < m && e == hipSuccess; ++j) {
+        const int64_t p0 = offsets_host[cut[j]], p1 = offsets_host[cut[j + 1]];
+        if (p1 > p0) {
+            e = hipMemcpyAsync(theta_dev + p0, theta_host + p0, (size_t)(p1 - p0) * sizeof(float),
+                               hipMemcpyHostToDevice, copy_st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(vd_dev + p0, vd_host + p0, (size_t)(p1 - p0) * sizeof(float),
+                                   hipMemcpyHostToDevice, copy_st);
+        }
+        if (e == hipSuccess) e = hipEventRecord(ev[j], copy_st);
+    }
+    for (int j = 0; j < m && e == hipSuccess && rc == RV_OK; ++j) {
+        e = hipStreamWaitEvent(st, ev[j], 0);
+        if (e != hipSuccess) break;
+        const int64_t c0 = cut[j], c1 = cut[j + 1];
+        const int64_t p0 = offsets_host[c0], p1 = offsets_host[c1];
+        rc = estimate_frame(theta_dev + p0, vd_dev + p0, offsets_dev + c0, c1 - c0, p1 - p0, n_hyp,
+                            tau, seed, vx + c0, vy + c0, heading + c0, n_inliers + c0,
+                            status + c0, n_near_tau != nullptr ? n_near_tau + c0 : nullptr,
+                            nullptr, hyp_counts != nullptr ? hyp_counts + c0 * n_hyp : nullptr,
+                            best_hyp != nullptr ? best_hyp + c0 : nullptr, workspace,
+                            workspace_bytes, (void *)st, (uint32_t)c0, p0, false);
+    }
+    give_events(dev, m, ev);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RV_ERR_HIP, "pipelined copy or wait failed: %s", hipGetErrorString(e));
+    }
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2060,7 +2190,40 @@ int rv_estimate_velocity(const float *theta, const float *vd, const int32_t *clu
     g_error[0] = '\0';
     return estimate_frame(theta, vd, cluster_offsets, n_clusters, n_points, n_hyp, tau, seed, vx,
                           vy, heading, n_inliers, status, n_near_tau, inlier_bits, hyp_counts,
-                          best_hyp, workspace, workspace_bytes, stream, true);
+                          best_hyp, workspace, workspace_bytes, stream, 0u, 0, true);
+}
+
+int rv_estimate_velocity_part(const float *theta, const float *vd, const int32_t *cluster_offsets,
+                              int64_t n_clusters, int64_t n_points, int64_t first_cluster,
+                              int64_t first_point, int32_t n_hyp, float tau, uint64_t seed,
+                              float *vx, float *vy, float *heading, int32_t *n_inliers,
+                              uint8_t *status, int32_t *n_near_tau, uint32_t *inlier_bits,
+                              int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                              size_t workspace_bytes, void *stream) {
+    g_error[0] = '\0';
+    if (first_cluster < 0 || first_cluster > (int64_t)UINT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "first_cluster must be in [0, 2^32 - 1]");
+    if (first_point < 0 || first_point > INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "first_point must be in [0, 2^31 - 1]");
+    return estimate_frame(theta, vd, cluster_offsets, n_clusters, n_points, n_hyp, tau, seed, vx,
+                          vy, heading, n_inliers, status, n_near_tau, inlier_bits, hyp_counts,
+                          best_hyp, workspace, workspace_bytes, stream, (uint32_t)first_cluster,
+                          first_point, true);
+}
+
+int rv_estimate_velocity_pipelined(const float *theta_host, const float *vd_host,
+                                   const int32_t *offsets_host, int64_t n_clusters,
+                                   int64_t n_points, int32_t n_parts, int32_t n_hyp, float tau,
+                                   uint64_t seed, float *theta_dev, float *vd_dev,
+                                   int32_t *offsets_dev, float *vx, float *vy, float *heading,
+                                   int32_t *n_inliers, uint8_t *status, int32_t *n_near_tau,
+                                   int32_t *hyp_counts, int32_t *best_hyp, void *workspace,
+                                   size_t workspace_bytes, void *stream, void *copy_stream) {
+    g_error[0] = '\0';
+    return estimate_pipelined(theta_host, vd_host, offsets_host, n_clusters, n_points, n_parts,
+                              n_hyp, tau, seed, theta_dev, vd_dev, offsets_dev, vx, vy, heading,
+                              n_inliers, status, n_near_tau, hyp_counts, best_hyp, workspace,
+                              workspace_bytes, (hipStream_t)stream, (hipStream_t)copy_stream);
 }
 
 int rv_estimate_velocity_noalloc(const float *theta, const float *vd,
@@ -2081,7 +2244,7 @@ int rv_estimate_velocity_noalloc(const float *theta, const float *vd,
     if (int rc = device_scratch((hipStream_t)stream, &ws)) return rc;
     return estimate_frame(theta, vd, cluster_offsets, n_clusters, n_points, n_hyp, tau, seed, vx,
                           vy, heading, n_inliers, status, n_near_tau, inlier_bits, hyp_counts,
-                          best_hyp, ws, RV_NOALLOC_SCRATCH_BYTES, stream, false);
+                          best_hyp, ws, RV_NOALLOC_SCRATCH_BYTES, stream, 0u, 0, false);
 }
 
 int rv_stage_timing(int enable) {

@@ -49,10 +49,12 @@ struct Span {
     bool ok;
 };
 
+// Points [off[k] - base, off[k+1] - base) of a frame's n_points; `base` is the
+// frame index of the first point when the frame is a part of a larger one.
 __device__ __forceinline__ Span cluster_span(const int32_t *__restrict__ off, int64_t k,
-                                             int64_t n_points) {
-    const int64_t a = off[k];
-    const int64_t b = off[k + 1];
+                                             int64_t n_points, int64_t base = 0) {
+    const int64_t a = off[k] - base;
+    const int64_t b = off[k + 1] - base;
     Span s;
     s.ok = a >= 0 && b >= a && b <= n_points;
     s.lo = s.ok ? a : 0;

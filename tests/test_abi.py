@@ -47,6 +47,7 @@ def test_header_constants_match_binding():
         assert getattr(binding, name) == int(value), name
     assert "RV_MIN_SEED_SEPARATION 1e-3" in text and binding.RV_MIN_SEED_SEPARATION == 1e-3
     assert "RV_NEAR_TAU_WINDOW 1e-5" in text and binding.RV_NEAR_TAU_WINDOW == 1e-5
+    assert "RV_MAX_PARTS 64" in text and binding.RV_MAX_PARTS == 64
 
 
 def test_noalloc_scratch_limit(lib):
@@ -286,3 +287,48 @@ def test_paper_variant_host_checks(lib):
         assert call(**kw) == code, kw
         assert word in lib.rv_last_error().decode()
     assert call(K=0, N=0, ws=fake, ws_bytes=1 << 20) == 0
+
+
+def test_part_first_cluster_checks(lib):
+    # The part entry point refuses a cluster or point base outside its range
+    # before any HIP call (fake pointers: never used).
+    fake = ctypes.c_void_p(4096)
+
+    def part(first, K=4, first_point=0):
+        return lib.rv_estimate_velocity_part(fake, fake, fake, K, 100, first, first_point, 16, 0.15,
+                                             1, fake, fake, fake, fake, fake, None, None, None,
+                                             None, fake, 1 << 20, None)
+
+    assert part(-1) == -1 and "first_cluster" in lib.rv_last_error().decode()
+    assert part(1 << 32) == -1 and "first_cluster" in lib.rv_last_error().decode()
+    assert part((1 << 32) - 2) == -1 and "2^32" in lib.rv_last_error().decode()
+    assert part(0, first_point=-1) == -1 and "first_point" in lib.rv_last_error().decode()
+    assert part(0, first_point=1 << 31) == -1 and "first_point" in lib.rv_last_error().decode()
+
+
+def test_pipelined_host_checks(lib):
+    # The pipelined entry point reads the host offsets to cut the frame: bad
+    # offsets, part counts and workspaces are refused before any HIP call.
+    import numpy as np
+
+    from paper_2012_12618_amd import binding
+
+    fake = ctypes.c_void_p(4096)
+    theta = np.zeros(100, np.float32)
+
+    def call(off, n_parts=4, n_points=100, ws_bytes=1 << 30):
+        off = np.ascontiguousarray(off, np.int32)
+        return lib.rv_estimate_velocity_pipelined(
+            ctypes.c_void_p(theta.ctypes.data), ctypes.c_void_p(theta.ctypes.data),
+            ctypes.c_void_p(off.ctypes.data), len(off) - 1, n_points, n_parts, 16, 0.15, 1, fake,
+            fake, fake, fake, fake, fake, fake, fake, None, None, None, fake, ws_bytes, None,
+            None)
+
+    good = [0, 10, 40, 100]
+    assert call(good, n_parts=0) == -1 and "n_parts" in lib.rv_last_error().decode()
+    assert call(good, n_parts=binding.RV_MAX_PARTS + 1) == -1
+    assert call([1, 10, 40, 100]) == -1 and "start at 0" in lib.rv_last_error().decode()
+    assert call([0, 10, 40, 99]) == -1 and "end at n_points" in lib.rv_last_error().decode()
+    assert call([0, 50, 40, 100]) == -1 and "decrease at cluster 1" in lib.rv_last_error().decode()
+    assert call(good, ws_bytes=64) == -2
+    assert call([0], n_points=0) == 0  # no clusters: nothing to do, nothing enqueued

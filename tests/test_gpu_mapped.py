@@ -107,3 +107,12 @@ def test_pageable_memory_is_refused(rv):
     with pytest.raises(ValueError, match="pinned"):
         rv.rv_estimate_velocity(torch.zeros(10), torch.zeros(10),
                                 torch.tensor([0, 10], dtype=torch.int32).pin_memory(), 4, 0.15, 1)
+
+
+def test_views_map_at_their_offset(rv):
+    # A view into pinned memory maps to the allocation's device address plus
+    # the view's byte offset (host-side queries only).
+    t = torch.empty(4096, dtype=torch.float32).pin_memory()
+    base = rv.host_device_pointer(t)
+    for off in (1, 5, 1000, 4095):
+        assert rv.host_device_pointer(t[off:]) == base + 4 * off, off
