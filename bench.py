@@ -51,7 +51,8 @@ WORKLOAD_TEXT["paper-sweep"] = (
     "20% uniform outliers, 256 trials per cluster, FP64")
 WORKLOAD_TEXT["issue-rates"] = (
     "wave64 issue rates of the scoring loops' instructions (v_fma_f32, compares, v_dot2_f32_f16, "
-    "the scalar popcount) and of the float32 and FP16 scoring rows, eight waves per SIMD "
+    "the scalar popcount), of the float32 and FP16 scoring rows, and of the hypothesis "
+    "generation's v_mad_u64_u32, v_mul_hi_u32 and v_fma_f64, eight waves per SIMD "
     "(_lib/issue_probe)")
 FRAME_WORKLOADS = ("dense", "small")
 

@@ -4,7 +4,8 @@
 // Each kernel runs ITER iterations of 16 independent copies of one instruction
 // (or of one scoring row: the float32 row of the estimator, two v_fma_f32 and a
 // compare whose 64-lane mask the scalar unit popcounts, and the FP16 row, one
-// v_dot2_f32_f16 and a compare).  The only memory access is one store per
+// v_dot2_f32_f16 and a compare), and of the hypothesis generation's integer
+// and FP64 instructions.  The only memory access is one store per
 // thread into an array of grid x block words.  Prints one JSON object: for each
 // case the kernel time, wave64 vector instructions per SIMD-cycle and
 // SIMD-cycles per instruction, scalar instructions per CU-cycle, and CU-cycles
@@ -187,6 +188,43 @@ __global__ __launch_bounds__(kBlock) void k_row_f16(float *out, u32 nd, float t)
     out[blockIdx.x * kBlock + threadIdx.x] = (float)n;
 }
 
+// The integer and FP64 instructions of a hypothesis's generation: the
+// 32x32->64 multiply-add of each Philox round, a 32-bit high product, and the
+// FP64 fused multiply-add of the seed solve.
+__global__ __launch_bounds__(kBlock) void k_mad_u64(float *out, u32 a) {
+    u64 x[16];
+    for (int i = 0; i < 16; ++i) x[i] = threadIdx.x + i;
+    for (int it = 0; it < kIter; ++it) {
+        RV_PROBE_16(u64 carry; asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0"
+                                            : "+v"(x[i]), "=s"(carry) : "v"((u32)x[i]), "v"(a)))
+    }
+    u64 s = 0;
+    for (int i = 0; i < 16; ++i) s += x[i];
+    out[blockIdx.x * kBlock + threadIdx.x] = (float)(s & 0xFFFF);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mul_hi_u32(float *out, u32 a) {
+    u32 x[16];
+    for (int i = 0; i < 16; ++i) x[i] = threadIdx.x + i;
+    for (int it = 0; it < kIter; ++it) {
+        RV_PROBE_16(asm volatile("v_mul_hi_u32 %0, %1, %0" : "+v"(x[i]) : "v"(a)))
+    }
+    u32 s = 0;
+    for (int i = 0; i < 16; ++i) s += x[i];
+    out[blockIdx.x * kBlock + threadIdx.x] = (float)s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fma_f64(float *out, double a, double b) {
+    double x[16];
+    for (int i = 0; i < 16; ++i) x[i] = threadIdx.x * 0.001 + i;
+    for (int it = 0; it < kIter; ++it) {
+        RV_PROBE_16(asm volatile("v_fma_f64 %0, %1, %2, %0" : "+v"(x[i]) : "v"(a), "v"(b)))
+    }
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) s += x[i];
+    out[blockIdx.x * kBlock + threadIdx.x] = (float)s;
+}
+
 struct Case {
     const char *name;
     int valu_per_iter, salu_per_iter, rows_per_iter;
@@ -204,6 +242,9 @@ const Case kCases[] = {
     {"s_bcnt1_i32_b64 + s_add_i32", 0, 32, 0},
     {"float32 row: 2 v_fma_f32 + v_cmp | s_bcnt1 + s_add", 48, 32, 16},
     {"FP16 row: v_dot2_f32_f16 + v_cmp | s_bcnt1 + s_add", 32, 32, 16},
+    {"v_mad_u64_u32", 16, 0, 0},
+    {"v_mul_hi_u32", 16, 0, 0},
+    {"v_fma_f64", 16, 0, 0},
 };
 
 hipError_t launch(int which, unsigned grid, float *out) {
@@ -220,6 +261,9 @@ hipError_t launch(int which, unsigned grid, float *out) {
         case 8: hipLaunchKernelGGL(k_salu, g, b, 0, 0, out, 0x123456789ABCDEFull); break;
         case 9: hipLaunchKernelGGL(k_row_f32, g, b, 0, 0, out, 0.1f, 0.2f, 0.15f); break;
         case 10: hipLaunchKernelGGL(k_row_f16, g, b, 0, 0, out, 0x00010001u, 0.15f); break;
+        case 11: hipLaunchKernelGGL(k_mad_u64, g, b, 0, 0, out, 0xD2511F53u); break;
+        case 12: hipLaunchKernelGGL(k_mul_hi_u32, g, b, 0, 0, out, 0xCD9E8D57u); break;
+        case 13: hipLaunchKernelGGL(k_fma_f64, g, b, 0, 0, out, 1.0000001, 1e-9); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

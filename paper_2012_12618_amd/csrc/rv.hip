@@ -1062,20 +1062,29 @@ __device__ __forceinline__ RefitLoads refit_load(Span sp, int64_t p0, int64_t st
     return L;
 }
 
+__device__ __forceinline__ void refit_group(const RefitLoads &L, int64_t p0, int64_t stride,
+                                            int64_t end, const Hypothesis &hy, double dtau,
+                                            RefitSums &a, const Outputs &o, int lane) {
+#pragma unroll
+    for (int u = 0; u < kRefitUnroll; ++u)
+        if (p0 + u * stride < end)
+            refit_points(p0 + u * stride, L.in[u], L.v[u], cs64(L.hi[u], L.lo[u]), hy, dtau, a, o,
+                         lane);
+}
+
+// The first group's loads come from the caller (issued before the hypothesis
+// solve); the first group is taken apart from the loop so that no copy of a
+// whole group of loads is selected at run time (such a select puts the group
+// in scratch memory).
 __device__ __forceinline__ RefitSums refit_sweep(Span sp, int64_t first_block, int64_t stride,
                                                  const RefitLoads &first, const Points &pts,
                                                  const Hypothesis &hy, double dtau,
                                                  const Outputs &o, int lane) {
     RefitSums a;
     const int64_t end = sp.lo + sp.n;
-    for (int64_t p0 = first_block; p0 < end; p0 += kRefitUnroll * stride) {
-        const RefitLoads L = p0 == first_block ? first : refit_load(sp, p0, stride, pts, lane);
-#pragma unroll
-        for (int u = 0; u < kRefitUnroll; ++u)
-            if (p0 + u * stride < end)
-                refit_points(p0 + u * stride, L.in[u], L.v[u], cs64(L.hi[u], L.lo[u]), hy, dtau,
-                             a, o, lane);
-    }
+    refit_group(first, first_block, stride, end, hy, dtau, a, o, lane);
+    for (int64_t p0 = first_block + kRefitUnroll * stride; p0 < end; p0 += kRefitUnroll * stride)
+        refit_group(refit_load(sp, p0, stride, pts, lane), p0, stride, end, hy, dtau, a, o, lane);
     return a;
 }
 
