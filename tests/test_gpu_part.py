@@ -152,3 +152,57 @@ def test_pipelined_matches_whole_frame(rv, case):
             torch.cuda.synchronize()
             got = {k: v.cpu().numpy() for k, v in got.items()}
             _same(f"pipelined {n_parts} {host_out}", got, whole, 0, K, H)
+
+
+def test_pipelined_edge_frames(rv):
+    # Empty and one-point clusters at the cuts, one cluster larger than a part,
+    # more parts than clusters, a frame of empty clusters only: every output as
+    # the whole-frame call's, and nothing to do for a frame without clusters.
+    rng = np.random.default_rng(606)
+
+    def cluster(n):
+        th = np.deg2rad(rng.uniform(-60, 60, n)).astype(np.float32)
+        vx, vy = rng.uniform(-30, 30, 2)
+        v = vx * np.cos(th.astype(np.float64)) + vy * np.sin(th.astype(np.float64))
+        v = v + rng.normal(0, 0.05, n)
+        out = rng.random(n) < 0.2
+        v[out] = rng.uniform(-40, 40, out.sum())
+        return th, v.astype(np.float32)
+
+    frames = {
+        "mixed": [0, 1, 5, 0, 200, 1, 3000, 2, 0, 64, 65, 0],
+        "few-clusters": [700, 3, 900],
+        "all-empty": [0, 0, 0, 0],
+        "one-cluster": [4097],
+    }
+    H, tau = 96, 0.15
+    copy_stream = torch.cuda.Stream()
+    for name, sizes in frames.items():
+        parts = [cluster(n) for n in sizes]
+        th = np.concatenate([p[0] for p in parts])
+        vd = np.concatenate([p[1] for p in parts])
+        off = np.zeros(len(sizes) + 1, np.int32)
+        off[1:] = np.cumsum(sizes)
+        K, N = len(sizes), int(off[-1])
+        print(f"[gpu] rv_estimate_velocity whole edge {name} K={K} N={N}", flush=True)
+        whole = rv.rv_estimate_velocity(torch.from_numpy(th).cuda(), torch.from_numpy(vd).cuda(),
+                                        torch.from_numpy(off).cuda(), H, tau, 0x606,
+                                        want_near=True, debug=True)
+        torch.cuda.synchronize()
+        whole = {k: v.cpu().numpy() for k, v in whole.items()}
+        h_t = torch.from_numpy(th).pin_memory()
+        h_v = torch.from_numpy(vd).pin_memory()
+        h_o = torch.from_numpy(off).pin_memory()
+        for n_parts in (1, 2, 5, rv.RV_MAX_PARTS):
+            print(f"[gpu] rv_estimate_velocity_pipelined edge {name} parts={n_parts}", flush=True)
+            got = rv.rv_estimate_velocity_pipelined(h_t, h_v, h_o, n_parts, H, tau, 0x606,
+                                                    debug=True, copy_stream=copy_stream)
+            torch.cuda.synchronize()
+            got = {k: v.cpu().numpy() for k, v in got.items()}
+            _same(f"edge {name} {n_parts}", got, whole, 0, K, H)
+    empty = torch.zeros(0, dtype=torch.float32).pin_memory()
+    got = rv.rv_estimate_velocity_pipelined(empty, empty,
+                                            torch.zeros(1, dtype=torch.int32).pin_memory(), 4,
+                                            H, tau, 1, copy_stream=copy_stream)
+    torch.cuda.synchronize()
+    assert all(v.numel() == 0 for v in got.values())
