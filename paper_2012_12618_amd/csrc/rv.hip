@@ -423,22 +423,36 @@ __device__ __forceinline__ int lanes_tail(int64_t n) {
     return t < kTailLanesMax ? t : 0;
 }
 
-// Stages the tail points of sp (tail of them, block-uniform) into LDS; the
-// caller's next block barrier publishes them.
-__device__ __forceinline__ void stage_tail(const Points &pts, Span sp, int tail, TailShared &sh) {
+// One staged point held by a thread between its loads and its LDS store, so
+// that the loads can be issued before other long-latency work (a hypothesis's
+// seed loads) and stored after it.
+struct PointLoad {
+    float2 cs;
+    float v;
+};
+
+// Thread tid's point among the `count` points from `first` (a valid point of
+// the span for the other threads: every load is in bounds, none is used).
+__device__ __forceinline__ PointLoad load_point(const Points &pts, int64_t first, int count) {
     const int tid = threadIdx.x;
-    if (tid < ((tail + 3) & ~3)) {
-        float c = 0.0f, sn = 0.0f, v = __builtin_inff();  // a padding point never counts
-        if (tid < tail) {
-            const int64_t p = sp.lo + sp.n - tail + tid;
-            const float2 q = pts.cs32[p];
-            c = q.x;
-            sn = q.y;
-            v = pts.v32[p];
-        }
-        reinterpret_cast<float *>(sh.c)[tid] = c;
-        reinterpret_cast<float *>(sh.s)[tid] = sn;
-        reinterpret_cast<float *>(sh.v)[tid] = v;
+    const int64_t p = first + (tid < count ? tid : 0);
+    PointLoad L;
+    L.cs = pts.cs32[p];
+    L.v = pts.v32[p];
+    return L;
+}
+
+// Stores the points of load_point into LDS as float4 quads, padded to a
+// multiple of four with (0, 0, +inf), a point that never counts; the caller's
+// next block barrier publishes them.
+__device__ __forceinline__ void store_points(const PointLoad &L, int count, float4 *c, float4 *s,
+                                             float4 *v) {
+    const int tid = threadIdx.x;
+    if (tid < ((count + 3) & ~3)) {
+        const bool real = tid < count;
+        reinterpret_cast<float *>(c)[tid] = real ? L.cs.x : 0.0f;
+        reinterpret_cast<float *>(s)[tid] = real ? L.cs.y : 0.0f;
+        reinterpret_cast<float *>(v)[tid] = real ? L.v : __builtin_inff();
     }
 }
 
@@ -491,8 +505,11 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
         return;
     }
     const int tail = lanes_tail(sp.n);  // the same for the whole block
-    if (tail > 0) stage_tail(pts, sp, tail, s_tail);
     {
+        // The tail points' loads go out before the hypothesis's seed loads and
+        // are stored after its solve, so the two latencies overlap.
+        PointLoad tl;
+        if (tail > 0) tl = load_point(pts, sp.lo + sp.n - tail, tail);
         float hx = __builtin_nanf(""), hy = __builtin_nanf("");
         if (h < n_hyp) {
             const Hypothesis hyp = make_hypothesis(pts, sp, (uint32_t)h, id.local, id.key0, id.key1);
@@ -500,6 +517,7 @@ __device__ __forceinline__ void score_block(Span sp, ClusterId id, int b, int32_
             hy = (float)hyp.vy;
         }
         reinterpret_cast<float2 *>(s_hyp)[tid] = make_float2(hx, hy);
+        if (tail > 0) store_points(tl, tail, s_tail.c, s_tail.s, s_tail.v);
     }
     __syncthreads();
 
@@ -755,18 +773,9 @@ __device__ __forceinline__ void score_block_lanes(Span sp, ClusterId id, int b, 
     const int tid = threadIdx.x;
     const int n = (int)sp.n;
     const int n4 = (n + 3) / 4;
-    if (tid < 4 * n4) {  // a padding point: e = +inf, never below tau
-        float c = 0.0f, sn = 0.0f, v = __builtin_inff();
-        if (tid < n) {
-            const float2 q = pts.cs32[sp.lo + tid];
-            c = q.x;
-            sn = q.y;
-            v = pts.v32[sp.lo + tid];
-        }
-        reinterpret_cast<float *>(sh.c)[tid] = c;
-        reinterpret_cast<float *>(sh.s)[tid] = sn;
-        reinterpret_cast<float *>(sh.v)[tid] = v;
-    }
+    // The point loads go out before the hypothesis's seed loads and are stored
+    // after its solve, so the two latencies overlap.
+    const PointLoad pl = load_point(pts, sp.lo, n);
     const int64_t h = (int64_t)b * kScoreBlock + tid;
     float hx = __builtin_nanf(""), hy = __builtin_nanf("");
     if (h < n_hyp) {
@@ -774,6 +783,7 @@ __device__ __forceinline__ void score_block_lanes(Span sp, ClusterId id, int b, 
         hx = (float)hyp.vx;  // NaN exactly when the pair is degenerate: counts 0
         hy = (float)hyp.vy;
     }
+    store_points(pl, n, sh.c, sh.s, sh.v);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int lane = tid % kWave;
