@@ -332,3 +332,20 @@ def test_pipelined_host_checks(lib):
     assert call([0, 50, 40, 100]) == -1 and "decrease at cluster 1" in lib.rv_last_error().decode()
     assert call(good, ws_bytes=64) == -2
     assert call([0], n_points=0) == 0  # no clusters: nothing to do, nothing enqueued
+
+
+def test_pipelined_binding_checks(lib):
+    # The binding refuses device or strided host inputs and wrong dtypes
+    # before it touches the GPU.
+    import torch
+
+    from paper_2012_12618_amd import binding
+
+    th = torch.zeros(64, dtype=torch.float32)
+    off = torch.tensor([0, 64], dtype=torch.int32)
+    with pytest.raises(ValueError, match="contiguous host tensor"):
+        binding.rv_estimate_velocity_pipelined(th[::2], th[::2], off, 2, 16, 0.15, 1)
+    with pytest.raises(TypeError, match="float32"):
+        binding.rv_estimate_velocity_pipelined(th.double(), th, off, 2, 16, 0.15, 1)
+    with pytest.raises(TypeError, match="int32"):
+        binding.rv_estimate_velocity_pipelined(th, th, off.long(), 2, 16, 0.15, 1)
