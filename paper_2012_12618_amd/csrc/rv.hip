@@ -3,7 +3,8 @@
 //
 // A single-frame call enqueues three kernels on the caller's stream:
 //   prep    one thread per point: FP64 sincos of the azimuth; stages float32
-//           (cos, sin) and v_d for scoring and FP64 (cos, sin) for the solves;
+//           (cos, sin) and v_d for scoring and the float32 low parts of the
+//           FP64 (cos, sin) for the solves and the refit;
 //           clears the optional frame-wide inlier bitmask and the per-cluster
 //           best keys.  Its first workgroup plans the dispatch order: clusters
 //           by decreasing size.
@@ -27,7 +28,10 @@
 //           hypothesis, FP64 normal-equation sums in a fixed reduction tree,
 //           2x2 solve (Sec. 3.2, Eq. 7, Alg. 2) and atan2 heading (Eq. 8).
 // Small frames without an inlier mask take one launch (small_frame_kernel)
-// that runs the same three steps per cluster in one workgroup.  The batched
+// that runs the same three steps per cluster in one workgroup.  A part of a
+// frame (its clusters drawing with their whole-frame indexes, its points found
+// through the frame's offsets minus a point base) runs the same kernels; a
+// frame in host memory can be copied and estimated part by part.  The batched
 // form stages, orders and describes the clusters of many frames, scores them
 // from per-XCD work queues in one persistent launch (optionally in the FP16
 // residual form) and refits them in one more launch.
