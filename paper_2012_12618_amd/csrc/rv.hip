@@ -2104,9 +2104,9 @@ void give_events(int dev, int n, const hipEvent_t *ev) {
     for (int i = 0; i < n; ++i) g_events[dev].push_back(ev[i]);
 }
 
-// Clusters [cut[j], cut[j+1]) form part j: the first cluster whose end reaches
-// j/n_parts of the points starts a new part (empty parts are dropped).  Returns
-// the number of parts.
+// Clusters [cut[j], cut[j+1]) form part j: the first cluster that starts at or
+// after point j * n_points / n_parts starts a new part (parts without clusters
+// are dropped).  Returns the number of parts.
 int cut_parts(const int32_t *off, int64_t n_clusters, int64_t n_points, int n_parts,
               int64_t *cut) {
     int m = 0;
