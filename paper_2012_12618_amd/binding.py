@@ -303,7 +303,8 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
     ``theta``/``vd``: float32 [N] on a GPU; ``offsets``: int32 [K+1] on the same
     device.  Inputs and the tensors of ``out`` may instead be pinned host
     tensors (the kernels then read and write them directly, no copies; the
-    call runs on the current GPU and the workspace stays there).  Outputs (and
+    call runs on the current GPU and the workspace stays there; the caller
+    keeps such tensors alive until the stream has finished with them).  Outputs (and
     the workspace) are allocated with torch unless ``out`` (from
     ``allocate_outputs``) is given.  Work is enqueued on ``stream`` (default:
     torch's current stream); the returned tensors are ready after that stream
@@ -388,8 +389,10 @@ def rv_estimate_velocity_pipelined(theta: torch.Tensor, vd: torch.Tensor, offset
     to overlap; ``device_inputs``: (theta, vd, offsets) device tensors of at
     least the frame's sizes that receive the copies (allocated if None).  The
     results (no inlier mask) are those of rv_estimate_velocity on the whole
-    frame; ``out`` may hold device or pinned host tensors.  The host tensors
-    must stay unchanged until ``stream`` has finished."""
+    frame; ``out`` may hold device or pinned host tensors.  The caller keeps
+    the host tensors alive and unchanged until ``stream`` has finished: the
+    library's copies read them then, and torch's pinned-memory cache does not
+    know of those copies, so it could hand freed memory out again too early."""
     lib = load_library()
     for name, t in (("theta", theta), ("vd", vd), ("offsets", offsets)):
         if t.device.type != "cpu" or not t.is_contiguous():
