@@ -23,6 +23,15 @@ if ROOT not in sys.path:
 
 METRIC = "clusters/s + hyp-point evals/s (% FP32 VALU peak); p50/p99 frame latency"
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2 x 2 x 2.4 GHz
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+# Algorithmic HBM bytes of the two other stages of the three-kernel path: the
+# staging reads theta and v_d and writes float32 (cos, sin), v_d and the low
+# parts (8 + 20 B per point); the refit reads v_d, (cos, sin) and the low parts
+# (20 B per point) and writes vx, vy, heading, n_inliers, n_near_tau and status
+# (21 B per cluster).
+PREP_BYTES_PER_POINT = 28
+REFIT_BYTES_PER_POINT = 20
+REFIT_BYTES_PER_CLUSTER = 21
 FLOP_PER_EVAL = 4                # two fused multiply-adds per hypothesis-point residual
 
 WORKLOAD_TEXT = {
@@ -1122,6 +1131,14 @@ def frame_bench(args, torch, binding, synth, dev, name) -> dict:
                      "algorithmic_flop_per_launch": FLOP_PER_EVAL * evals,
                      "kernel_ms": score_ms, "kernel_events_on_steps": n_calls,
                      "valu_issue": profiled_valu_issue(name) if kernel == "score_kernel" else None},
+        "stage_roofline": None if small_path else {
+            st: {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
+                 "unit": "GB/s", "frac": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                 "algorithmic_bytes_per_launch": b, "kernel_ms": ms}
+            for st, b, ms in (
+                ("prep", PREP_BYTES_PER_POINT * N, stage_avg[binding.STAGE_NAMES.index("prep")]),
+                ("refit", REFIT_BYTES_PER_POINT * N + REFIT_BYTES_PER_CLUSTER * K,
+                 stage_avg[binding.STAGE_NAMES.index("refit")]))},
         "cpu_baseline": cpu,
     }
     return line
