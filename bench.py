@@ -359,7 +359,7 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
 def pipelined_latency(torch, binding, dev, stream, frame_at, n_frames, n_hyp, tau, n_parts,
                       buffers, res, name, synth):
     """Host-clock latency of the frames of latency_run sent and estimated in
-    n_parts parts of about equal points by rv_estimate_velocity_pipelined: part
+    n_parts parts (shrinking toward the end) by rv_estimate_velocity_pipelined: part
     j's estimate runs on the compute stream while part j + 1 is copied on a copy
     stream, and the per-cluster results are written straight into pinned host
     memory through its device mapping.  The clock covers the call (cutting the
@@ -1046,7 +1046,7 @@ def frame_bench(args, torch, binding, synth, dev, name) -> dict:
     # Large frames are also sent in parts, each part's estimate overlapping the next one's copy.
     lat, lat_recipe, lat_z, lat_p = latency_run(
         torch, binding, synth, dev, stream, name, frame, n_hyp, tau, args.latency_frames,
-        zero_copy=small_path, pipelined_parts=() if small_path else (2, 4, 8))
+        zero_copy=small_path, pipelined_parts=() if small_path else (2, 3, 4, 8))
 
     calibration_copy(torch, dev, args.copy_calibration_mb)
 

@@ -156,10 +156,12 @@ int rv_estimate_velocity_part(const float *theta, const float *vd, const int32_t
 
 /*
  * rv_estimate_velocity_pipelined: one frame from host memory, copied to the
- * GPU and estimated in n_parts parts of about equal points (cut at cluster
- * boundaries), part j's estimate (rv_estimate_velocity_part) running on
- * `stream` while part j + 1 is copied on `copy_stream`.  The outputs are bit
- * for bit those of rv_estimate_velocity on the whole frame.
+ * GPU and estimated in n_parts parts cut at cluster boundaries, part j's
+ * estimate (rv_estimate_velocity_part) running on `stream` while part j + 1 is
+ * copied on `copy_stream`.  Part j holds about a share n_parts - j out of
+ * n_parts (n_parts + 1) / 2 of the points: the parts shrink toward the end,
+ * since only the last part's estimate is not hidden behind a copy.  The
+ * outputs are bit for bit those of rv_estimate_velocity on the whole frame.
  *   theta_host, vd_host [n_points], offsets_host [n_clusters + 1]: host memory,
  *     pinned (hipHostMalloc, torch's pin_memory()) for the copies to run
  *     asynchronously.  The host reads offsets_host during the call to cut the

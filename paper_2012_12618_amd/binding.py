@@ -383,7 +383,8 @@ def rv_estimate_velocity_pipelined(theta: torch.Tensor, vd: torch.Tensor, offset
                                    stream: torch.cuda.Stream | None = None,
                                    copy_stream: torch.cuda.Stream | None = None) -> dict:
     """One frame from host memory, copied and estimated in ``n_parts`` parts
-    (rv_estimate_velocity_pipelined): each part's estimate on ``stream``
+    that shrink toward the end (rv_estimate_velocity_pipelined): each part's
+    estimate on ``stream``
     overlaps the next part's copy on ``copy_stream`` (default: a new stream).
     ``theta``/``vd``/``offsets``: contiguous CPU tensors, pinned for the copies
     to overlap; ``device_inputs``: (theta, vd, offsets) device tensors of at

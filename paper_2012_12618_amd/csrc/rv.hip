@@ -2104,16 +2104,20 @@ void give_events(int dev, int n, const hipEvent_t *ev) {
     for (int i = 0; i < n; ++i) g_events[dev].push_back(ev[i]);
 }
 
-// Clusters [cut[j], cut[j+1]) form part j: the first cluster that starts at or
-// after point j * n_points / n_parts starts a new part (parts without clusters
-// are dropped).  Returns the number of parts.
+// Clusters [cut[j], cut[j+1]) form part j.  Part j gets a share of the points
+// proportional to n_parts - j (shares P, P - 1, ..., 1 out of P (P + 1) / 2):
+// only the last part's estimate is not hidden behind a later copy, so the
+// parts shrink toward the end.  The first cluster that starts at or after part
+// j's first point starts it (parts without clusters are dropped).  Returns the
+// number of parts.
 int cut_parts(const int32_t *off, int64_t n_clusters, int64_t n_points, int n_parts,
               int64_t *cut) {
     int m = 0;
     cut[m++] = 0;
     int64_t k = 0;
+    const int64_t total = (int64_t)n_parts * (n_parts + 1);
     for (int j = 1; j < n_parts; ++j) {
-        const int64_t target = n_points * j / n_parts;
+        const int64_t target = n_points * ((int64_t)j * (2 * n_parts - j + 1)) / total;
         while (k < n_clusters && off[k] < target) ++k;
         if (k > cut[m - 1] && k < n_clusters) cut[m++] = k;
     }
