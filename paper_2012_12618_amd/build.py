@@ -1,8 +1,9 @@
 """Build the gfx950 shared library ``_lib/librv.so`` from ``csrc/rv.hip`` (kernels
 and estimator entry points), ``csrc/rv_paper.hip`` (paper-literal variant) and
-``csrc/rv_server.cpp`` (frame server), and the measurement program
+``csrc/rv_server.cpp`` (frame server); the measurement program
 ``_lib/issue_probe`` from ``csrc/issue_probe.hip`` (instruction issue rates,
-run by ``bench.py --workload issue-rates``).
+run by ``bench.py --workload issue-rates``); and ``_lib/rv_cli`` from
+``csrc/rv_cli.cpp`` (a frame from raw files through the C ABI alone).
 
 Usage: ``python -m paper_2012_12618_amd.build`` (also called by the repository's
 ``__graft_entry__.build()``).  hipcc cross-compiles for gfx950 without a GPU.
@@ -22,6 +23,8 @@ LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "librv.so")
 PROBE_SRC = os.path.join(HERE, "csrc", "issue_probe.hip")
 PROBE = os.path.join(LIB_DIR, "issue_probe")
+CLI_SRC = os.path.join(HERE, "csrc", "rv_cli.cpp")
+CLI = os.path.join(LIB_DIR, "rv_cli")
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -61,6 +64,9 @@ def build(verbose: bool = False, extra_flags: list[str] | None = None) -> str:
     probe_flags = [f for f in HIP_FLAGS if f not in ("-fPIC", "-shared")]
     _hipcc([hipcc_path(), *probe_flags, "-o", PROBE + ".tmp", PROBE_SRC], verbose)
     os.replace(PROBE + ".tmp", PROBE)
+    _hipcc([hipcc_path(), *probe_flags, "-I", INCLUDE, "-o", CLI + ".tmp", CLI_SRC, "-L", LIB_DIR,
+            "-lrv", "-Wl,-rpath,$ORIGIN"], verbose)
+    os.replace(CLI + ".tmp", CLI)
     return LIB
 
 
