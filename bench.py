@@ -546,12 +546,16 @@ def batch_bench(args, torch, binding, synth, dev) -> dict:
     return line
 
 
-def served_bench(args, torch, binding, synth, dev, extra_fp16: int = 0) -> dict:
+def served_bench(args, torch, binding, synth, dev, extra_fp16: int = 0,
+                 zero_copy: bool = False) -> dict:
     """Served form: paced arrivals for latency, then the same frames as fast as
     the server takes them for throughput; the per-frame form (one frame per
     launch, one slot) on the same traffic for comparison.  extra_fp16 > 0: the
     served form also runs in the FP16 residual form for clusters of at least
-    that many points ("served_fp16_form"), against the same per-frame run."""
+    that many points ("served_fp16_form"), against the same per-frame run.
+    zero_copy: the served and per-frame forms also run with every frame held
+    in pinned host memory and queued without a copy (RVServer.submit_pinned;
+    "served_zero_copy_form", "per_frame_zero_copy_form")."""
     from paper_2012_12618_amd import serve
 
     name = args.workload
@@ -582,26 +586,33 @@ def served_bench(args, torch, binding, synth, dev, extra_fp16: int = 0) -> dict:
         return synth.frame_seed(name, a.index)
 
     out = {}
-    forms = [("served", 64, 2, args.fp16_min_points)]
+    forms = [("served", 64, 2, args.fp16_min_points, False)]
     if extra_fp16 > 0:
-        forms.append(("served_fp16", 64, 2, extra_fp16))
-    forms.append(("per_frame", 1, 1, 0))
-    for form, max_batch, n_streams, fp16_min in forms:
+        forms.append(("served_fp16", 64, 2, extra_fp16, False))
+    forms.append(("per_frame", 1, 1, 0, False))
+    pinned = None
+    if zero_copy:
+        forms += [("served_zero_copy", 64, 2, args.fp16_min_points, True),
+                  ("per_frame_zero_copy", 1, 1, 0, True)]
+        pinned = [tuple(torch.from_numpy(a).pin_memory() for a in (f.theta, f.vd, f.offsets))
+                  for f in frames]
+    for form, max_batch, n_streams, fp16_min, zc in forms:
         server = make_server(max_batch, n_streams, fp16_min)
+        pf = pinned if zc else None
         try:
             print(f"[bench] {form}: warmup", file=sys.stderr, flush=True)
             serve.run_traffic(server, frames, warm, seed_of, n_hyp, paced=False,
-                              submitters=args.submitters)
+                              submitters=args.submitters, pinned_frames=pf)
             print(f"[bench] {form}: {len(schedule)} paced arrivals over {args.duration} s",
                   file=sys.stderr, flush=True)
             paced, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=True,
-                                         submitters=args.submitters)
+                                         submitters=args.submitters, pinned_frames=pf)
             print(f"[bench] {form}: same arrivals unpaced", file=sys.stderr, flush=True)
             if form == "served":
                 binding.rv_stage_times()
                 binding.rv_stage_timing(True)
             sat, _ = serve.run_traffic(server, frames, schedule, seed_of, n_hyp, paced=False,
-                                       submitters=args.submitters)
+                                       submitters=args.submitters, pinned_frames=pf)
             if form == "served":
                 binding.rv_stage_timing(False)
                 out["stages"] = binding.rv_stage_times()
@@ -670,6 +681,12 @@ def served_bench(args, torch, binding, synth, dev, extra_fp16: int = 0) -> dict:
     if extra_fp16 > 0:
         paced_h, sat_h, _ = out["served_fp16"]
         line["served_fp16_form"] = dict(brief(paced_h, sat_h), fp16_min_points=extra_fp16)
+    if zero_copy:
+        scope = ("frames held in pinned host memory, queued without a copy "
+                 "(RVServer.submit_pinned); results back in host memory")
+        for form in ("served_zero_copy", "per_frame_zero_copy"):
+            paced_z, sat_z, _ = out[form]
+            line[form + "_form"] = dict(brief(paced_z, sat_z), scope=scope)
     return line
 
 
@@ -1208,15 +1225,19 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
     a.workload = "served"
     a.duration = args.extras_duration
     a.fp16_min_points = 0
-    sv = served_bench(a, torch, binding, synth, dev, extra_fp16=256)
+    sv = served_bench(a, torch, binding, synth, dev, extra_fp16=256, zero_copy=True)
     pf = sv["per_frame_form"]
     out["served"] = {
         "workload": WORKLOAD_TEXT["served"] + "; the served form in float32 and in the FP16 "
                     "residual form for clusters of at least 256 points (outputs bitwise equal), "
-                    "the per-frame form in float32, all on the same arrivals",
+                    "the per-frame form in float32, all on the same arrivals; then the served "
+                    "and per-frame forms again with the frames in pinned host memory, queued "
+                    "without a copy",
         "duration_s": a.duration, "arrivals": sv["config"]["frames"],
         "served_form": sv["served_form"], "served_fp16_form": sv["served_fp16_form"],
         "per_frame_form": pf,
+        "served_zero_copy_form": sv["served_zero_copy_form"],
+        "per_frame_zero_copy_form": sv["per_frame_zero_copy_form"],
         "served_over_per_frame_clusters_per_s":
             sv["served_form"]["saturated"]["clusters_per_s"] / pf["saturated"]["clusters_per_s"],
         "p99_served_over_per_frame":
@@ -1224,7 +1245,10 @@ def default_extras(args, torch, binding, synth, dev) -> dict:
         "served_fp16_over_per_frame_clusters_per_s":
             sv["served_fp16_form"]["saturated"]["clusters_per_s"] / pf["saturated"]["clusters_per_s"],
         "p99_served_fp16_over_per_frame":
-            sv["served_fp16_form"]["latency_ms"]["p99"] / pf["latency_ms"]["p99"]}
+            sv["served_fp16_form"]["latency_ms"]["p99"] / pf["latency_ms"]["p99"],
+        "p99_served_over_per_frame_zero_copy":
+            sv["served_zero_copy_form"]["latency_ms"]["p99"]
+            / sv["per_frame_zero_copy_form"]["latency_ms"]["p99"]}
     return out
 
 

@@ -352,7 +352,8 @@ int rv_estimate_velocity_paper(const float *theta, const float *vd, const int32_
  * A server owns one device arena of hbm_budget_bytes (allocated once, at
  * creation), a pool of pinned host buffers, n_streams launch slots and two
  * threads.  rv_server_submit copies a frame from caller HOST memory into a
- * pinned buffer and queues it.  The scheduler thread admits waiting frames in
+ * pinned buffer and queues it (rv_server_submit_pinned queues a frame held in
+ * the caller's pinned memory without copying it).  The scheduler thread admits waiting frames in
  * arrival order whenever a launch slot is free: as many as fit, together, in
  * the arena's largest free range (inputs, workspace and outputs of the batch)
  * and in max_batch_frames; it copies them to the device and launches them as
@@ -409,6 +410,21 @@ int rv_server_submit(rv_server_t *server, const float *theta, const float *vd,
                      const int32_t *cluster_offsets, int64_t n_clusters, int64_t n_points,
                      uint64_t seed, uint64_t *ticket);
 
+/*
+ * rv_server_submit without the copy: theta, vd and cluster_offsets are host
+ * arrays that the server reads in place, the offsets on the host when the
+ * frame's batch is launched and the points by the batch's host-to-device
+ * copies.  They should be pinned (hipHostMalloc, torch's pin_memory()) for
+ * those copies to be asynchronous; pageable arrays give the same results, with
+ * copies that hold the server's scheduler thread.  The caller keeps them alive
+ * and unchanged until rv_server_wait reports the ticket ready (or the ticket's
+ * batch fails); several frames in flight may share read-only arrays.  Errors
+ * and results as rv_server_submit, the results bit for bit.
+ */
+int rv_server_submit_pinned(rv_server_t *server, const float *theta, const float *vd,
+                            const int32_t *cluster_offsets, int64_t n_clusters, int64_t n_points,
+                            uint64_t seed, uint64_t *ticket);
+
 /* Waits up to timeout_ms (negative: no limit) for a ticket's results: 1 ready,
    0 not yet, RV_ERR_INVALID_ARG for an unknown ticket, RV_ERR_HIP if its batch
    failed. */
@@ -416,7 +432,7 @@ int rv_server_wait(rv_server_t *server, uint64_t ticket, int64_t timeout_ms);
 
 /* Host-clock times of one frame, nanoseconds since the server's creation. */
 typedef struct {
-    int64_t submitted_ns;   /* rv_server_submit copied it */
+    int64_t submitted_ns;   /* rv_server_submit copied it (queued it, without a copy) */
     int64_t launched_ns;    /* its batch was enqueued */
     int64_t done_ns;        /* its batch's results were in host memory */
     int32_t batch_frames;   /* frames in its batch */

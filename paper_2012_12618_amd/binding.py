@@ -173,6 +173,8 @@ def load_library() -> ctypes.CDLL:
     lib.rv_server_create.argtypes = [P, P]
     lib.rv_server_submit.restype = ctypes.c_int
     lib.rv_server_submit.argtypes = [P, P, P, P, i64, i64, ctypes.c_uint64, P]
+    lib.rv_server_submit_pinned.restype = ctypes.c_int
+    lib.rv_server_submit_pinned.argtypes = [P, P, P, P, i64, i64, ctypes.c_uint64, P]
     lib.rv_server_wait.restype = ctypes.c_int
     lib.rv_server_wait.argtypes = [P, ctypes.c_uint64, i64]
     lib.rv_server_result.restype = ctypes.c_int
@@ -745,8 +747,10 @@ def rv_server_frame_bytes(cfg: RVServerConfig, n_clusters: int, n_points: int) -
 class RVServer:
     """rv_server_t: frames in host memory in, per-cluster results in host memory out.
 
-    Submit copies the frame before returning; ``result`` returns numpy arrays.
-    The arena and the threads live until ``destroy`` (or garbage collection).
+    Submit copies the frame before returning (``submit_pinned`` queues a frame
+    held in pinned host tensors without copying it); ``result`` returns numpy
+    arrays.  The arena and the threads live until ``destroy`` (or garbage
+    collection).
     """
 
     def __init__(self, cfg: RVServerConfig | None = None, **overrides):
@@ -761,6 +765,7 @@ class RVServer:
         _check(lib.rv_server_create(ctypes.byref(self.cfg), ctypes.byref(handle)))
         self._h = handle
         self._sizes: dict[int, tuple[int, int]] = {}
+        self._pinned: dict[int, tuple] = {}  # tensors a queued frame is read from
 
     def submit(self, theta: np.ndarray, vd: np.ndarray, offsets: np.ndarray, seed: int) -> int:
         """Queue one frame; returns its ticket.  Raises RVError (code RV_ERR_BUSY when full)."""
@@ -776,6 +781,30 @@ class RVServer:
             offsets.ctypes.data_as(ctypes.c_void_p), n_clusters, n_points,
             int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(t)))
         self._sizes[int(t.value)] = (n_clusters, n_points)
+        return int(t.value)
+
+    def submit_pinned(self, theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
+                      seed: int) -> int:
+        """Queue one frame held in host tensors (float32 theta and vd, int32
+        offsets), read in place by the server: no copy.  Pinned tensors
+        (pin_memory()) keep the server's copies asynchronous; they are not
+        checked here, since the pointer query costs more than the copy saves.
+        The tensors are referenced until ``result`` takes the ticket; the
+        caller leaves their contents unchanged until then."""
+        for name, t, dt in (("theta", theta, torch.float32), ("vd", vd, torch.float32),
+                            ("offsets", offsets, torch.int32)):
+            if t.device.type != "cpu" or not t.is_contiguous() or t.dtype != dt:
+                raise ValueError(f"{name} must be a contiguous {dt} host tensor")
+        n_points, n_clusters = int(theta.numel()), int(offsets.numel()) - 1
+        if int(vd.numel()) != n_points or n_clusters < 0:
+            raise ValueError("theta and vd must have the same length; offsets needs >= 1 entry")
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else None  # noqa: E731
+        t = ctypes.c_uint64()
+        _check(load_library().rv_server_submit_pinned(
+            self._h, ptr(theta), ptr(vd), ptr(offsets), n_clusters, n_points,
+            int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(t)))
+        self._sizes[int(t.value)] = (n_clusters, n_points)
+        self._pinned[int(t.value)] = (theta, vd, offsets)
         return int(t.value)
 
     def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
@@ -802,6 +831,7 @@ class RVServer:
             ptr(out["n_inliers"]), ptr(out["status"]), ptr(out["n_near_tau"]),
             ptr(out["best_hyp"]), None if bits is None else ptr(bits), ctypes.byref(times)))
         del self._sizes[int(ticket)]
+        self._pinned.pop(int(ticket), None)
         if bits is not None:
             out["inlier_bits"] = bits
         out["times"] = {n: int(getattr(times, n)) for n, _ in RVFrameTimes._fields_}

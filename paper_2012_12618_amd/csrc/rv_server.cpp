@@ -180,8 +180,10 @@ enum FrameState { kWaiting = 0, kLaunched = 1, kDone = 2, kFailed = 3 };
 struct Frame {
     int64_t K = 0, N = 0;
     uint64_t seed = 0;
-    void *in = nullptr;  // pinned: theta[N] | vd[N] | offsets[K + 1]
-    size_t in_cap = 0;
+    void *in = nullptr;  // the server's pinned copy: theta[N] | vd[N] | offsets[K + 1];
+    size_t in_cap = 0;   // null when the frame is read from the caller's pinned arrays
+    const float *src_theta = nullptr, *src_vd = nullptr;  // where the frame is read from
+    const int32_t *src_off = nullptr;
     int64_t c0 = 0, p0 = 0;  // first cluster and point in its batch
     int state = kWaiting;
     rv_frame_times_t times{};
@@ -190,9 +192,9 @@ struct Frame {
     std::vector<uint8_t> status;
     std::vector<uint32_t> bits;  // its inlier mask, when the server keeps masks
 
-    const float *theta() const { return (const float *)in; }
-    const float *vd() const { return (const float *)in + N; }
-    const int32_t *offsets() const { return (const int32_t *)((const float *)in + 2 * N); }
+    const float *theta() const { return src_theta; }
+    const float *vd() const { return src_vd; }
+    const int32_t *offsets() const { return src_off; }
 };
 
 struct Slot {
@@ -484,6 +486,82 @@ void release_all(rv_server *s) {
 
 }  // namespace
 
+namespace {
+
+// Queues a frame read from the server's pinned copy (copy = true) or straight
+// from the caller's arrays.  The caller's arrays are not checked for being
+// pinned: a pointer query per array costs the runtime's lock, which the
+// scheduler and completion threads also take; pageable arrays are still copied
+// correctly, only synchronously.
+int submit_frame(rv_server *s, const float *theta, const float *vd,
+                 const int32_t *cluster_offsets, int64_t n_clusters, int64_t n_points,
+                 uint64_t seed, uint64_t *ticket, bool copy) {
+    g_error[0] = '\0';
+    if (s == nullptr || ticket == nullptr) return fail(RV_ERR_INVALID_ARG, "server or ticket is NULL");
+    if (n_clusters < 0 || n_clusters > INT32_MAX || n_points < 0 || n_points > INT32_MAX)
+        return fail(RV_ERR_INVALID_ARG, "n_clusters and n_points must be in [0, 2^31 - 1]");
+    if (cluster_offsets == nullptr || (n_points > 0 && (theta == nullptr || vd == nullptr)))
+        return fail(RV_ERR_INVALID_ARG, "theta, vd or cluster_offsets is NULL");
+    if (cluster_offsets[0] != 0 || cluster_offsets[n_clusters] != n_points)
+        return fail(RV_ERR_INVALID_ARG, "cluster_offsets must start at 0 and end at n_points");
+    for (int64_t k = 0; k < n_clusters; ++k)
+        if (cluster_offsets[k + 1] < cluster_offsets[k])
+            return fail(RV_ERR_INVALID_ARG, "cluster_offsets must be non-decreasing");
+    const size_t need = plan_for(s, 1, n_clusters, n_points).total;
+    if (need > s->cfg.hbm_budget_bytes)
+        return fail(RV_ERR_INVALID_ARG, "frame needs %zu bytes of device memory, budget is %zu",
+                    need, s->cfg.hbm_budget_bytes);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if ((int64_t)s->waiting.size() + s->reserved >= s->cfg.max_waiting_frames) {
+            s->st.busy_rejections += 1;
+            return fail(RV_ERR_BUSY, "%d frames are waiting", s->cfg.max_waiting_frames);
+        }
+        s->reserved += 1;
+    }
+    Frame *f = new Frame;
+    f->K = n_clusters;
+    f->N = n_points;
+    f->seed = seed;
+    if (copy) {
+        const size_t bytes = 8 * (size_t)n_points + 4 * (size_t)(n_clusters + 1);
+        f->in = s->pool.get(bytes, &f->in_cap);
+        if (f->in == nullptr) {
+            delete f;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->reserved -= 1;
+            return fail(RV_ERR_HIP, "pinned host allocation of %zu bytes failed", bytes);
+        }
+        float *in = (float *)f->in;
+        if (n_points > 0) {
+            memcpy(in, theta, 4 * (size_t)n_points);
+            memcpy(in + n_points, vd, 4 * (size_t)n_points);
+        }
+        memcpy(in + 2 * n_points, cluster_offsets, 4 * (size_t)(n_clusters + 1));
+        f->src_theta = in;
+        f->src_vd = in + n_points;
+        f->src_off = (const int32_t *)(in + 2 * n_points);
+    } else {
+        f->src_theta = theta;
+        f->src_vd = vd;
+        f->src_off = cluster_offsets;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->reserved -= 1;
+        f->times.submitted_ns = s->now();
+        f->times.slot = -1;
+        *ticket = s->next_ticket++;
+        s->frames[*ticket] = f;
+        s->waiting.push_back(f);
+        s->st.frames_submitted += 1;
+    }
+    s->cv_sched.notify_one();
+    return RV_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void rv_server_config_default(rv_server_config_t *cfg) {
@@ -560,58 +638,13 @@ int rv_server_create(const rv_server_config_t *cfg, rv_server_t **server) {
 int rv_server_submit(rv_server_t *s, const float *theta, const float *vd,
                      const int32_t *cluster_offsets, int64_t n_clusters, int64_t n_points,
                      uint64_t seed, uint64_t *ticket) {
-    g_error[0] = '\0';
-    if (s == nullptr || ticket == nullptr) return fail(RV_ERR_INVALID_ARG, "server or ticket is NULL");
-    if (n_clusters < 0 || n_clusters > INT32_MAX || n_points < 0 || n_points > INT32_MAX)
-        return fail(RV_ERR_INVALID_ARG, "n_clusters and n_points must be in [0, 2^31 - 1]");
-    if (cluster_offsets == nullptr || (n_points > 0 && (theta == nullptr || vd == nullptr)))
-        return fail(RV_ERR_INVALID_ARG, "theta, vd or cluster_offsets is NULL");
-    if (cluster_offsets[0] != 0 || cluster_offsets[n_clusters] != n_points)
-        return fail(RV_ERR_INVALID_ARG, "cluster_offsets must start at 0 and end at n_points");
-    for (int64_t k = 0; k < n_clusters; ++k)
-        if (cluster_offsets[k + 1] < cluster_offsets[k])
-            return fail(RV_ERR_INVALID_ARG, "cluster_offsets must be non-decreasing");
-    const size_t need = plan_for(s, 1, n_clusters, n_points).total;
-    if (need > s->cfg.hbm_budget_bytes)
-        return fail(RV_ERR_INVALID_ARG, "frame needs %zu bytes of device memory, budget is %zu",
-                    need, s->cfg.hbm_budget_bytes);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if ((int64_t)s->waiting.size() + s->reserved >= s->cfg.max_waiting_frames) {
-            s->st.busy_rejections += 1;
-            return fail(RV_ERR_BUSY, "%d frames are waiting", s->cfg.max_waiting_frames);
-        }
-        s->reserved += 1;
-    }
-    Frame *f = new Frame;
-    f->K = n_clusters;
-    f->N = n_points;
-    f->seed = seed;
-    const size_t bytes = 8 * (size_t)n_points + 4 * (size_t)(n_clusters + 1);
-    f->in = s->pool.get(bytes, &f->in_cap);
-    if (f->in == nullptr) {
-        delete f;
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->reserved -= 1;
-        return fail(RV_ERR_HIP, "pinned host allocation of %zu bytes failed", bytes);
-    }
-    if (n_points > 0) {
-        memcpy(f->in, theta, 4 * (size_t)n_points);
-        memcpy((float *)f->in + n_points, vd, 4 * (size_t)n_points);
-    }
-    memcpy((float *)f->in + 2 * n_points, cluster_offsets, 4 * (size_t)(n_clusters + 1));
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->reserved -= 1;
-        f->times.submitted_ns = s->now();
-        f->times.slot = -1;
-        *ticket = s->next_ticket++;
-        s->frames[*ticket] = f;
-        s->waiting.push_back(f);
-        s->st.frames_submitted += 1;
-    }
-    s->cv_sched.notify_one();
-    return RV_OK;
+    return submit_frame(s, theta, vd, cluster_offsets, n_clusters, n_points, seed, ticket, true);
+}
+
+int rv_server_submit_pinned(rv_server_t *s, const float *theta, const float *vd,
+                            const int32_t *cluster_offsets, int64_t n_clusters, int64_t n_points,
+                            uint64_t seed, uint64_t *ticket) {
+    return submit_frame(s, theta, vd, cluster_offsets, n_clusters, n_points, seed, ticket, false);
 }
 
 int rv_server_wait(rv_server_t *s, uint64_t ticket, int64_t timeout_ms) {

@@ -80,7 +80,8 @@ class TrafficReport:
 
 
 def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_of,
-                n_hyp: int, *, paced: bool = True, keep_results: bool = False, submitters: int = 1):
+                n_hyp: int, *, paced: bool = True, keep_results: bool = False, submitters: int = 1,
+                pinned_frames=None):
     """Submit frames[a.radar] at each arrival's time (or as fast as the server
     takes them when paced is False) and collect every result.
 
@@ -90,6 +91,9 @@ def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_
     arrival to the return of its submit (the copy into pinned memory, plus any
     lateness of the submitting thread) plus the server's time from that copy to
     results in host memory.  seed_of(arrival) gives the frame's hypothesis seed.
+    With ``pinned_frames`` (per frame, (theta, vd, offsets) pinned host tensors
+    of the same values) the frames are queued without a copy
+    (RVServer.submit_pinned), as from a sensor driver that fills pinned buffers.
     Returns (report, results) where results maps arrival index -> result dict
     when keep_results.
     """
@@ -115,7 +119,10 @@ def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_
             start = time.perf_counter()
             while True:
                 try:
-                    tk = server.submit(f.theta, f.vd, f.offsets, seed_of(a))
+                    if pinned_frames is None:
+                        tk = server.submit(f.theta, f.vd, f.offsets, seed_of(a))
+                    else:
+                        tk = server.submit_pinned(*pinned_frames[a.radar], seed_of(a))
                     break
                 except binding.RVError as e:
                     if e.code != binding.RV_ERR_BUSY:

@@ -261,6 +261,7 @@ def test_server_host_checks(lib):
         assert word in lib.rv_last_error().decode() and not h.value
     t = ctypes.c_uint64()
     assert lib.rv_server_submit(None, None, None, None, 0, 0, 1, ctypes.byref(t)) == -1
+    assert lib.rv_server_submit_pinned(None, None, None, None, 0, 0, 1, ctypes.byref(t)) == -1
     assert lib.rv_server_wait(None, 1, 0) == -1
     assert lib.rv_server_result(None, 1, None, None, None, None, None, None, None, None,
                                 None) == -1

@@ -146,3 +146,39 @@ def test_full_queue_answers_busy(rv):
             server.result(tk)
     finally:
         server.destroy()
+
+
+def test_pinned_submit_matches_copied_submit(rv):
+    # Frames held in pinned host memory and queued without a copy give every
+    # output of the copied submit bit for bit; several tickets in flight read
+    # the same pinned arrays.
+    frames, H, tau = _frames()
+    cfg = rv.rv_server_config_default()
+    cfg.n_hyp, cfg.tau = H, tau
+    cfg.keep_inlier_bits = 1
+    cfg.max_batch_frames, cfg.n_streams = 4, 2
+    pinned = [tuple(torch.from_numpy(a).pin_memory() for a in (f.theta, f.vd, f.offsets))
+              for f in frames]
+    jobs = [(i % len(frames), synth.frame_seed("served", 700 + i)) for i in range(16)]
+    print(f"[gpu] server pinned submits jobs={len(jobs)}", flush=True)
+    server = rv.RVServer(cfg)
+    try:
+        t_pin = [server.submit_pinned(*pinned[fi], seed) for fi, seed in jobs]
+        t_cpy = [server.submit(frames[fi].theta, frames[fi].vd, frames[fi].offsets, seed)
+                 for fi, seed in jobs]
+        for j, (a, b) in enumerate(zip(t_pin, t_cpy)):
+            ra, rb = server.result(a), server.result(b)
+            for k in KEYS:
+                assert np.array_equal(ra[k].view(np.uint8), rb[k].view(np.uint8)), (j, k)
+        # Pageable arrays read in place give the same results (synchronous copies).
+        f = frames[0]
+        tp = server.submit_pinned(torch.from_numpy(f.theta), torch.from_numpy(f.vd),
+                                  torch.from_numpy(f.offsets), 4242)
+        tc = server.submit(f.theta, f.vd, f.offsets, 4242)
+        ra, rb = server.result(tp), server.result(tc)
+        for k in KEYS:
+            assert np.array_equal(ra[k].view(np.uint8), rb[k].view(np.uint8)), ("pageable", k)
+        with pytest.raises(ValueError, match="float32"):
+            server.submit_pinned(pinned[0][0].double(), *pinned[0][1:], 1)
+    finally:
+        server.destroy()
