@@ -1289,6 +1289,9 @@ def main() -> int:
                     help="served workload: threads submitting frames (radars dealt round-robin)")
     ap.add_argument("--duration", type=float, default=5.0,
                     help="served workload: seconds of simulated arrivals in the timed run")
+    ap.add_argument("--zero-copy-submit", action="store_true",
+                    help="served workload: also run the served and per-frame forms with the "
+                         "frames in pinned host memory, queued without a copy")
     ap.add_argument("--host-comparators", action="store_true",
                     help="paper-sweep: also time scikit-learn RANSACRegressor and numpy pinv per "
                          "cluster on the host (the paper's Table I/II comparators; context only)")
@@ -1336,7 +1339,8 @@ def main() -> int:
     dev = torch.device("cuda:0")
     name = args.workload
     if name == "served":
-        print(json.dumps(served_bench(args, torch, binding, synth, dev)), flush=True)
+        print(json.dumps(served_bench(args, torch, binding, synth, dev,
+                                      zero_copy=args.zero_copy_submit)), flush=True)
         return 0
     if name == "paper-sweep":
         return paper_sweep_bench(args, torch, binding, synth, dev)
