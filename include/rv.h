@@ -176,8 +176,9 @@ int rv_estimate_velocity_part(const float *theta, const float *vd, const int32_t
  *     rv_estimate_velocity or rv_estimate_velocity_part for the mask).
  *   n_parts in [1, RV_MAX_PARTS]; workspace as rv_estimate_velocity.
  *   copy_stream: a stream of the same device other than `stream` (the same
- *     stream is correct but overlaps nothing).  Its copies are ordered after
- *     the work already queued on it; the call makes `stream` wait for them.
+ *     stream is correct but overlaps nothing).  The call's copies wait for the
+ *     work already queued on `stream` and on copy_stream (so calls in a row
+ *     may reuse the device buffers), and `stream` waits for each part's copy.
  * The call returns once everything is enqueued; the results are ready when
  * `stream` is.
  */

@@ -2159,13 +2159,18 @@ int estimate_pipelined(const float *theta_host, const float *vd_host,
         return fail(RV_ERR_HIP, "device index %d outside [0, %d)", dev, kMaxDevices);
     int64_t cut[RV_MAX_PARTS + 1];
     const int m = cut_parts(offsets_host, n_clusters, n_points, n_parts, cut);
-    hipEvent_t ev[RV_MAX_PARTS];
-    int rc = take_events(dev, m, ev);
+    hipEvent_t ev[RV_MAX_PARTS + 1];
+    int rc = take_events(dev, m + 1, ev);
     if (rc != RV_OK) return rc;
-    // Every copy first, so that the copy engine never waits for the host; then
-    // each part's estimate behind its copy.
-    e = hipMemcpyAsync(offsets_dev, offsets_host, (size_t)(n_clusters + 1) * sizeof(int32_t),
-                       hipMemcpyHostToDevice, copy_st);
+    // The copies wait for the work already queued on `stream` (a previous
+    // call's estimates may still read the same device buffers); then every
+    // copy is enqueued first, so that the copy engine never waits for the
+    // host, and each part's estimate behind its copy.
+    e = hipEventRecord(ev[m], st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(copy_st, ev[m], 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(offsets_dev, offsets_host, (size_t)(n_clusters + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, copy_st);
     for (int j = 0; j < m && e == hipSuccess; ++j) {
         const int64_t p0 = offsets_host[cut[j]], p1 = offsets_host[cut[j + 1]];
         if (p1 > p0) {
@@ -2189,7 +2194,7 @@ int estimate_pipelined(const float *theta_host, const float *vd_host,
                             best_hyp != nullptr ? best_hyp + c0 : nullptr, workspace,
                             workspace_bytes, (void *)st, (uint32_t)c0, p0, false);
     }
-    give_events(dev, m, ev);
+    give_events(dev, m + 1, ev);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(RV_ERR_HIP, "pipelined copy or wait failed: %s", hipGetErrorString(e));

@@ -206,3 +206,30 @@ def test_pipelined_edge_frames(rv):
                                             H, tau, 1, copy_stream=copy_stream)
     torch.cuda.synchronize()
     assert all(v.numel() == 0 for v in got.values())
+
+
+def test_pipelined_calls_in_a_row_reuse_buffers(rv):
+    # Two pipelined calls enqueued back to back on the same device buffers,
+    # no synchronisation between them: the second call's copies wait for the
+    # first call's estimates, so both frames' results are the whole-frame ones.
+    spec = synth.FrameSpec(400, "loguniform", 8, 4096, p_uniform=0.15)
+    fa, fb = synth.make_frame(spec, 201), synth.make_frame(spec, 202)
+    H, tau = 1024, 0.15
+    N = max(fa.n_points, fb.n_points)
+    K = max(fa.n_clusters, fb.n_clusters)
+    dev_in = (torch.empty(N, device="cuda"), torch.empty(N, device="cuda"),
+              torch.empty(K + 1, dtype=torch.int32, device="cuda"))
+    copy_stream = torch.cuda.Stream()
+    outs = []
+    host = []
+    for f, seed in ((fa, 0x2011), (fb, 0x2022)):
+        h = tuple(torch.from_numpy(a).pin_memory() for a in (f.theta, f.vd, f.offsets))
+        host.append(h)  # kept alive until the stream is done
+        print(f"[gpu] rv_estimate_velocity_pipelined back to back K={f.n_clusters}", flush=True)
+        outs.append(rv.rv_estimate_velocity_pipelined(*h, 4, H, tau, seed, device_inputs=dev_in,
+                                                      debug=True, copy_stream=copy_stream))
+    torch.cuda.synchronize()
+    for (f, seed), got in zip(((fa, 0x2011), (fb, 0x2022)), outs):
+        whole = _whole(rv, f, H, tau, seed, bits=False)
+        got = {k: v.cpu().numpy() for k, v in got.items()}
+        _same(f"back-to-back {seed:#x}", got, whole, 0, f.n_clusters, H)
