@@ -315,13 +315,29 @@ int launch_slot(rv_server *s, Slot &sl) {
     }
     if (e != hipSuccess) return fail(RV_ERR_HIP, "hipMemcpyAsync failed: %s", hipGetErrorString(e));
     char *o = d + p.out;
-    const int rc = rv_estimate_velocity_batch(
-        (const float *)(d + p.theta), (const float *)(d + p.vd), (const int32_t *)(d + p.offsets),
-        (const int32_t *)(d + p.frame_off), (const uint64_t *)(d + p.seeds), F, sl.K, sl.N,
-        s->cfg.n_hyp, s->cfg.tau, (float *)(o + p.o_vx), (float *)(o + p.o_vy),
-        (float *)(o + p.o_heading), (int32_t *)(o + p.o_inl), (uint8_t *)(o + p.o_status),
-        (int32_t *)(o + p.o_near), p.bits_words > 0 ? (uint32_t *)(o + p.o_bits) : nullptr,
-        nullptr, (int32_t *)(o + p.o_best), &s->cfg.tuning, d + p.ws, p.ws_bytes, st);
+    int rc;
+    // A batch of one frame in float32 takes the single-frame launch sequence
+    // (three kernels, or one for a small frame, against the batched form's
+    // six): the same results bit for bit, fewer launches on the frame's path.
+    // Its workspace fits in the batched one (fewer bytes per cluster).
+    if (F == 1 && s->cfg.tuning.fp16_min_points == 0 &&
+        rv_workspace_bytes(sl.K, sl.N, s->cfg.n_hyp) <= p.ws_bytes)
+        rc = rv_estimate_velocity(
+            (const float *)(d + p.theta), (const float *)(d + p.vd),
+            (const int32_t *)(d + p.offsets), sl.K, sl.N, s->cfg.n_hyp, s->cfg.tau,
+            sl.frames[0]->seed, (float *)(o + p.o_vx), (float *)(o + p.o_vy),
+            (float *)(o + p.o_heading), (int32_t *)(o + p.o_inl), (uint8_t *)(o + p.o_status),
+            (int32_t *)(o + p.o_near), p.bits_words > 0 ? (uint32_t *)(o + p.o_bits) : nullptr,
+            nullptr, (int32_t *)(o + p.o_best), d + p.ws, p.ws_bytes, st);
+    else
+        rc = rv_estimate_velocity_batch(
+            (const float *)(d + p.theta), (const float *)(d + p.vd),
+            (const int32_t *)(d + p.offsets), (const int32_t *)(d + p.frame_off),
+            (const uint64_t *)(d + p.seeds), F, sl.K, sl.N, s->cfg.n_hyp, s->cfg.tau,
+            (float *)(o + p.o_vx), (float *)(o + p.o_vy), (float *)(o + p.o_heading),
+            (int32_t *)(o + p.o_inl), (uint8_t *)(o + p.o_status), (int32_t *)(o + p.o_near),
+            p.bits_words > 0 ? (uint32_t *)(o + p.o_bits) : nullptr, nullptr,
+            (int32_t *)(o + p.o_best), &s->cfg.tuning, d + p.ws, p.ws_bytes, st);
     if (rc != RV_OK) return rc;
     if (sl.K > 0) {
         e = hipMemcpyAsync(sl.result, o, p.out_bytes, hipMemcpyDeviceToHost, st);
