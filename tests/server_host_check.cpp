@@ -45,6 +45,15 @@ int rv_estimate_velocity_batch(const float *, const float *, const int32_t *, co
     fprintf(stderr, "the estimate must not run in the host check\n");
     abort();
 }
+size_t rv_workspace_bytes(int64_t n_clusters, int64_t n_points, int32_t) {
+    return (size_t)(20 * n_points + 12 * n_clusters + 1536);
+}
+int rv_estimate_velocity(const float *, const float *, const int32_t *, int64_t, int64_t, int32_t,
+                         float, uint64_t, float *, float *, float *, int32_t *, uint8_t *,
+                         int32_t *, uint32_t *, int32_t *, int32_t *, void *, size_t, void *) {
+    fprintf(stderr, "the estimate must not run in the host check\n");
+    abort();
+}
 }
 
 static int failures = 0;
