@@ -36,6 +36,14 @@ import numpy as np
 V_TOL = 1e-4
 
 
+def v_tolerance(ref_vx: float, ref_vy: float) -> float:
+    """Bound on |GPU - oracle| for vx and vy: 1e-4 m/s plus the float32
+    rounding of the outputs (half a unit in the last place, at most
+    2^-24 max(|vx|, |vy|)), which alone exceeds 1e-4 m/s above about 1680 m/s
+    (refits through a few nearly collinear points)."""
+    return V_TOL + 2.0 ** -24 * max(abs(ref_vx), abs(ref_vy))
+
+
 def unpack_bits(words: np.ndarray, n_points: int) -> np.ndarray:
     """int32/uint32 words (bit p%32 of word p/32 = point p) -> bool [n_points]."""
     w = np.ascontiguousarray(words).view(np.uint32)
@@ -179,7 +187,7 @@ def check(theta, vd, offsets, n_hyp, tau, seed, g: dict, o, *, check_hyp=True,
             continue
         dv = max(abs(float(g["vx"][i]) - ref_vx), abs(float(g["vy"][i]) - ref_vy))
         stats["max_dv"] = max(stats["max_dv"], dv)
-        assert dv <= V_TOL, f"cluster {k}: |dv| = {dv}"
+        assert dv <= v_tolerance(ref_vx, ref_vy), f"cluster {k}: |dv| = {dv}"
         speed = math.hypot(ref_vx, ref_vy)
         if speed >= 0.01:
             dh = abs(math.remainder(float(g["heading"][i]) - ref_hd, 2 * math.pi))

@@ -99,6 +99,23 @@ def test_parity_random_frames(rv, oracle_mod, H):
     _parity(oracle_mod, f"random-H{H}", th, vd, off, H, 0.15, 0xABCD0000 + H)
 
 
+@pytest.mark.parametrize("case", range(6))
+def test_parity_random_shapes(rv, oracle_mod, case):
+    # Frames of the synthetic generator with drawn shapes: cluster count, size
+    # law and range, outlier fractions (uniform and micro-Doppler band), noise,
+    # H and tau.
+    rng = np.random.default_rng(7000 + case)
+    lo = int(rng.integers(2, 40))
+    spec = synth.FrameSpec(int(rng.integers(1, 120)), ("uniform", "loguniform")[case % 2], lo,
+                           int(rng.integers(lo, 1500)), p_uniform=float(rng.uniform(0.0, 0.5)),
+                           p_band=float(rng.uniform(0.0, 0.3)), sigma=float(rng.uniform(0.01, 0.2)))
+    frame = synth.make_frame(spec, 7100 + case)
+    H = int(rng.choice([1, 33, 256, 513, 1024]))
+    tau = float(np.float32(rng.choice([0.05, 0.15, 0.4])))
+    _parity(oracle_mod, f"random-shape-{case}", frame.theta, frame.vd, frame.offsets, H, tau,
+            0x7000 + case)
+
+
 def test_parity_row_and_pass_boundaries(rv, oracle_mod):
     rng = np.random.default_rng(77)
     sizes = [2, 3, 63, 64, 65, 127, 128, 129, 1023, 1024, 1025, 1088, 2047, 2048, 2049, 3000]

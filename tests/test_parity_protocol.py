@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import parity
+from paper_2012_12618_amd import synth
 from test_oracle_band import _clusters, _pair_hypotheses
 
 H, SEED = 2048, 0x5EED
@@ -97,3 +98,34 @@ def test_mask_difference_near_tau_is_refit_on_the_gpu_mask(oracle_mod, frame):
     g2["mask"][lo + far[0]] = True
     with pytest.raises(AssertionError, match="not near tau"):
         parity.check(th, vd, off, H, tau, SEED, g2, o)
+
+
+def test_velocity_bound_includes_the_float32_rounding(oracle_mod):
+    # One hypothesis per cluster: some refits pass through two nearly collinear
+    # points and give thousands of m/s, whose float32 outputs cannot lie within
+    # 1e-4 of the FP64 refit.  The oracle's own results rounded to float32 pass;
+    # an error beyond the bound fails.
+    rng = np.random.default_rng(7003)  # the shape drawn by the GPU random-shape case 3
+    lo = int(rng.integers(2, 40))
+    spec = synth.FrameSpec(int(rng.integers(1, 120)), "loguniform", lo, int(rng.integers(lo, 1500)),
+                           p_uniform=float(rng.uniform(0.0, 0.5)),
+                           p_band=float(rng.uniform(0.0, 0.3)), sigma=float(rng.uniform(0.01, 0.2)))
+    f = synth.make_frame(spec, 7103)
+    tau = float(np.float32(0.15))
+    o = oracle_mod.estimate_velocity(f.theta, f.vd, f.offsets, 1, tau, 0x7003, debug=True)
+    speed = np.abs(np.nan_to_num(o.vx)) + np.abs(np.nan_to_num(o.vy))
+    k = int(np.argmax(speed))
+    big = max(abs(o.vx[k]), abs(o.vy[k]))
+    assert big > 1700 and o.status[k] == 0
+    g = _as_gpu(o)
+    assert max(abs(float(g["vx"][k]) - o.vx[k]), abs(float(g["vy"][k]) - o.vy[k])) > parity.V_TOL \
+        or np.spacing(np.float32(big)) / 2 > parity.V_TOL
+    parity.check(f.theta, f.vd, f.offsets, 1, tau, 0x7003, g, o)
+    g2 = _as_gpu(o)
+    worse = 2 * parity.v_tolerance(o.vx[k], o.vy[k])
+    if abs(o.vx[k]) >= abs(o.vy[k]):
+        g2["vx"][k] = np.float32(o.vx[k] + worse)
+    else:
+        g2["vy"][k] = np.float32(o.vy[k] + worse)
+    with pytest.raises(AssertionError, match="dv"):
+        parity.check(f.theta, f.vd, f.offsets, 1, tau, 0x7003, g2, o)
