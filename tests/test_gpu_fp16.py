@@ -133,6 +133,24 @@ def _stress_frame():
                        kind=np.zeros(int(offsets[-1]), np.int8))
 
 
+@pytest.mark.parametrize("case", range(6))
+def test_fp16_form_equals_float32_form_random_shapes(rv, case):
+    # One frame of drawn shape (sizes, outliers, noise, H, tau) in the FP16 form
+    # for every cluster of at least two points against the float32 form.
+    rng = np.random.default_rng(8000 + case)
+    lo = int(rng.integers(2, 60))
+    spec = synth.FrameSpec(int(rng.integers(1, 80)), ("uniform", "loguniform")[case % 2], lo,
+                           int(rng.integers(lo, 6000)), p_uniform=float(rng.uniform(0.0, 0.6)),
+                           p_band=float(rng.uniform(0.0, 0.4)), sigma=float(rng.uniform(0.01, 0.3)))
+    frame = synth.make_frame(spec, 8100 + case)
+    H = int(rng.choice([1, 64, 257, 1024]))
+    tau = float(np.float32(rng.choice([0.02, 0.15, 1.0])))
+    fo, seeds = _single_frame(frame, 8200 + case)
+    g32 = _run(rv, frame, fo, seeds, H, tau, 0, f"float32 shape {case}")
+    g16 = _run(rv, frame, fo, seeds, H, tau, 2, f"fp16 shape {case}")
+    _compare(frame, H, g32, g16, 2, f"random shape {case} H={H} tau={tau}")
+
+
 def test_fp16_form_on_stress_clusters(rv, oracle_mod):
     frame = _stress_frame()
     fo, seeds = _single_frame(frame, 1)
