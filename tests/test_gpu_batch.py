@@ -89,6 +89,42 @@ def test_batch_equals_single_frames(rv):
         assert np.array_equal(g["mask"][p0:p0 + fr.n_points], s["mask"]), f
 
 
+@pytest.mark.parametrize("case", range(3))
+def test_batch_of_drawn_shapes_equals_single_frames(rv, case):
+    # Frames of drawn shapes (cluster count, size law and range, outliers,
+    # noise) in one batch with drawn lanes and rows tuning: every output of
+    # every frame equals its single-frame call's bit for bit.
+    rng = np.random.default_rng(9000 + case)
+    frames = []
+    for f in range(int(rng.integers(2, 9))):
+        lo = int(rng.integers(2, 50))
+        spec = synth.FrameSpec(int(rng.integers(0, 150)), ("uniform", "loguniform")[f % 2], lo,
+                               int(rng.integers(lo, 3000)), p_uniform=float(rng.uniform(0, 0.5)),
+                               p_band=float(rng.uniform(0, 0.3)), sigma=float(rng.uniform(0.01, 0.2)))
+        frames.append(synth.make_frame(spec, 9100 + 10 * case + f))
+    fo = np.zeros(len(frames) + 1, np.int64)
+    fo[1:] = np.cumsum([fr.n_clusters for fr in frames])
+    seeds = np.array([synth.frame_seed("batched", 9200 + 10 * case + i) for i in range(len(frames))],
+                     np.uint64)
+    batch = synth.Batch(frame=synth.concat_frames(frames), frame_offsets=fo.astype(np.int32),
+                        seeds=seeds)
+    H = int(rng.choice([1, 100, 256, 700]))
+    tau = float(np.float32(rng.choice([0.05, 0.15, 0.5])))
+    tuning = rv.rv_tuning_default()
+    tuning.lanes_max_points = int(rng.choice([0, 32, 64, 256]))
+    for b in range(len(tuning.rows_max)):
+        tuning.rows_max[b] = int(rng.integers(1, 17))
+    g = _run_batch(rv, batch, H, tau, f"drawn-{case}", tuning=tuning)
+    for f, fr in enumerate(frames):
+        c0, c1 = int(fo[f]), int(fo[f + 1])
+        p0 = int(batch.frame.offsets[c0])
+        s = parity.run_gpu(fr.theta, fr.vd, fr.offsets, H, tau, int(seeds[f]), label=f"drawn{case}-{f}")
+        for k in KEYS:
+            assert np.array_equal(g[k][c0:c1], s[k], equal_nan=k in ("vx", "vy", "heading")), (f, k)
+        assert np.array_equal(g["hyp_counts"][c0 * H:c1 * H], s["hyp_counts"]), f
+        assert np.array_equal(g["mask"][p0:p0 + fr.n_points], s["mask"]), f
+
+
 def test_batch_parity_with_oracle(rv, oracle_mod):
     batch, H, tau = synth.make_batch_workload("served", n_frames=3)
     g = _run_batch(rv, batch, H, tau, "oracle")
