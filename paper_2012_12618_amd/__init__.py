@@ -18,7 +18,7 @@ _BINDING_NAMES = (
     "RVServer", "RVServerConfig", "rv_server_config_default", "rv_server_frame_bytes",
     "rv_estimate_velocity_paper", "rv_paper_workspace_bytes", "rv_estimate_velocity_part",
     "rv_estimate_velocity_pipelined", "rv_estimate_velocity_noalloc",
-    "host_device_pointer", "PreparedEstimate",
+    "host_device_pointer", "PreparedEstimate", "estimate_velocity",
 )
 
 __all__ = list(_BINDING_NAMES)

@@ -319,6 +319,11 @@ def rv_estimate_velocity(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.T
                      out, stream, validate)
 
 
+# The estimate under its short name, estimate_velocity(theta, vd, offsets, n_hyp,
+# tau, seed, *, debug=False, ...): the same function.
+estimate_velocity = rv_estimate_velocity
+
+
 def rv_estimate_velocity_part(theta: torch.Tensor, vd: torch.Tensor, offsets: torch.Tensor,
                               first_cluster: int, first_point: int, n_hyp: int, tau: float,
                               seed: int, *, want_near: bool = True, want_bits: bool = False,

@@ -350,3 +350,14 @@ def test_pipelined_binding_checks(lib):
         binding.rv_estimate_velocity_pipelined(th.double(), th, off, 2, 16, 0.15, 1)
     with pytest.raises(TypeError, match="int32"):
         binding.rv_estimate_velocity_pipelined(th, th, off.long(), 2, 16, 0.15, 1)
+
+
+def test_package_exports():
+    # Every name the package lists resolves to the binding's object without
+    # loading the library; estimate_velocity is rv_estimate_velocity.
+    import paper_2012_12618_amd as rv
+    from paper_2012_12618_amd import binding
+
+    for name in rv.__all__:
+        assert getattr(rv, name) is getattr(binding, name), name
+    assert rv.estimate_velocity is binding.rv_estimate_velocity
