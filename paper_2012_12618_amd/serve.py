@@ -13,6 +13,7 @@ Arrivals: every radar sends frames as a Poisson process of rate ``fps``
 from __future__ import annotations
 
 import dataclasses
+import gc
 import threading
 import time
 
@@ -72,7 +73,8 @@ class TrafficReport:
                            "p99": percentile(self.latency_ms, 99),
                            "max": max(self.latency_ms)},
             "server_latency_ms": {"p50": percentile(self.server_latency_ms, 50),
-                                  "p99": percentile(self.server_latency_ms, 99)},
+                                  "p99": percentile(self.server_latency_ms, 99),
+                                  "max": max(self.server_latency_ms)},
             "mean_batch_frames": float(np.mean(self.batch_frames)),
             "busy_retries": self.busy_retries, "late_submits": self.late_submits,
             "server": self.stats,
@@ -140,32 +142,42 @@ def run_traffic(server: binding.RVServer, frames, schedule: list[Arrival], seed_
             running[0] -= 1
             cond.notify()
 
-    t0 = time.perf_counter() + 0.01
-    parts = [[a for a in schedule if a.radar % submitters == i] for i in range(submitters)]
-    threads = [threading.Thread(target=submitter, args=(t0, part), daemon=True) for part in parts]
-    for th in threads:
-        th.start()
-    got = 0
-    t_last = t0
-    while True:
-        with cond:
-            while got >= len(tickets) and running[0] > 0:
-                cond.wait()
-            if got >= len(tickets):
-                break
-            tk, a, pre = tickets[got]
-        r = server.result(tk)
-        t_last = time.perf_counter()
-        tm = r["times"]
-        server_ms = (tm["done_ns"] - tm["submitted_ns"]) * 1e-6
-        lat.append(pre * 1e3 + server_ms)
-        slat.append(server_ms)
-        bsz.append(tm["batch_frames"])
-        if keep_results:
-            results[a.index] = r
-        got += 1
-    for th in threads:
-        th.join()
+    # Python's cyclic garbage collector stays off while the traffic runs: a full
+    # collection holds every thread of the process (the submitters included)
+    # for tens of milliseconds, which would count against the frame in flight.
+    gc_was_enabled = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter() + 0.01
+        parts = [[a for a in schedule if a.radar % submitters == i] for i in range(submitters)]
+        threads = [threading.Thread(target=submitter, args=(t0, part), daemon=True)
+                   for part in parts]
+        for th in threads:
+            th.start()
+        got = 0
+        t_last = t0
+        while True:
+            with cond:
+                while got >= len(tickets) and running[0] > 0:
+                    cond.wait()
+                if got >= len(tickets):
+                    break
+                tk, a, pre = tickets[got]
+            r = server.result(tk)
+            t_last = time.perf_counter()
+            tm = r["times"]
+            server_ms = (tm["done_ns"] - tm["submitted_ns"]) * 1e-6
+            lat.append(pre * 1e3 + server_ms)
+            slat.append(server_ms)
+            bsz.append(tm["batch_frames"])
+            if keep_results:
+                results[a.index] = r
+            got += 1
+        for th in threads:
+            th.join()
+    finally:
+        if gc_was_enabled:
+            gc.enable()
     if errors:
         raise errors[0]
     clusters = sum(frames[a.radar].n_clusters for a in schedule)
