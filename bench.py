@@ -256,6 +256,23 @@ def sum_evals(frame, n_hyp):
     return synth.evals_per_frame(frame.offsets, n_hyp)
 
 
+def timed_frames(call, name, n_frames):
+    """call(i, seed) for the n_frames timed frames, with Python's cyclic
+    garbage collector off meanwhile (a full collection would stall the timing
+    thread for milliseconds and count against one frame)."""
+    import gc
+
+    from paper_2012_12618_amd import synth
+
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        return [call(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    finally:
+        if was:
+            gc.enable()
+
+
 def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_frames,
                 zero_copy=False, pipelined_parts=()):
     """Host-clock latency of n_frames distinct frames, each from pinned host
@@ -323,7 +340,7 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
 
     for i in range(min(8, n_frames)):  # untimed first use of the buffers
         one(i, synth.ransac_seed(name, 9_000 + i))
-    lat = [one(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    lat = timed_frames(one, name, n_frames)
     pipe = {P: pipelined_latency(torch, binding, dev, stream, frame_at, n_frames, n_hyp, tau, P,
                                  (h_t, h_v, d_t, d_v), res, name, synth)
             for P in pipelined_parts}
@@ -352,7 +369,7 @@ def latency_run(torch, binding, synth, dev, stream, name, frame, n_hyp, tau, n_f
 
     for i in range(min(8, n_frames)):
         zero(i, synth.ransac_seed(name, 9_000 + i))
-    lat_z = [zero(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    lat_z = timed_frames(zero, name, n_frames)
     return lat, recipe, lat_z, pipe
 
 
@@ -406,7 +423,7 @@ def pipelined_latency(torch, binding, dev, stream, frame_at, n_frames, n_hyp, ta
                               whole[key].cpu().numpy().view(np.uint8)) for key in keys)
     for i in range(1, min(8, n_frames)):
         run(i, synth.ransac_seed(name, 9_000 + i))
-    lat = [run(i, synth.ransac_seed(name, 10_000 + i)) for i in range(n_frames)]
+    lat = timed_frames(run, name, n_frames)
     return lat, same
 
 
