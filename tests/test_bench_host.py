@@ -3,7 +3,9 @@
 * more than one GPU is refused with a message (this estimator runs on one GPU);
 * the kernel-code hash ignores comments and blank lines but not code;
 * a committed counter summary is read back only while the kernel code is the
-  code it was taken on.
+  code it was taken on;
+* the latency loops run every frame with a fresh seed and Python's garbage
+  collector off, and turn it back on.
 """
 import os
 import subprocess
@@ -69,3 +71,21 @@ def test_oracle_error_summary_per_cluster_bound():
     assert e["dv_within_float32_rounding"] == 2
     assert abs(e["abs_dv_mps"]["max"] - 1e-6) < 1e-8
     assert e["abs_dheading_rad"]["max"] < 1e-5
+
+
+def test_timed_frames_runs_every_frame_with_the_collector_off():
+    import gc
+
+    seen = []
+
+    def call(i, seed):
+        seen.append((i, seed, gc.isenabled()))
+        return float(i)
+
+    assert gc.isenabled()
+    out = bench.timed_frames(call, "small", 5)
+    assert out == [0.0, 1.0, 2.0, 3.0, 4.0]
+    assert [s[0] for s in seen] == list(range(5))
+    assert len({s[1] for s in seen}) == 5  # a fresh seed per frame
+    assert not any(s[2] for s in seen)
+    assert gc.isenabled()  # restored afterwards
