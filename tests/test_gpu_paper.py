@@ -94,6 +94,24 @@ def test_small_and_dense_like_frames(rv, oracle_mod):
     _compare(g, o, f.offsets, 128)
 
 
+@pytest.mark.parametrize("case", range(4))
+def test_drawn_shapes(rv, oracle_mod, case):
+    # Frames of drawn shape (cluster count, sizes up to the variant's limit,
+    # outliers, noise, H) against the variant's own oracle, on both paths.
+    rng = np.random.default_rng(9500 + case)
+    lo = int(rng.integers(2, 40))
+    spec = synth.FrameSpec(int(rng.integers(1, 100)), ("uniform", "loguniform")[case % 2], lo,
+                           int(rng.integers(lo, 4097)), p_uniform=float(rng.uniform(0, 0.5)),
+                           p_band=float(rng.uniform(0, 0.3)), sigma=float(rng.uniform(0.01, 0.2)))
+    f = synth.make_frame(spec, 9600 + case)
+    H = int(rng.choice([1, 50, 256, 600]))
+    seed = 9700 + case
+    o = oracle_mod.estimate_velocity_paper(f.theta, f.vd, f.offsets, H, seed, debug=True)
+    for bits in (True, False):
+        g = _run(rv, f.theta, f.vd, f.offsets, H, seed, f"drawn {case} bits={bits}", bits=bits)
+        _compare(g, o, f.offsets, H)
+
+
 def _edge_frame(rv):
     # one point, equal azimuths, a NaN point, zero Doppler span, an empty
     # cluster, a cluster of RV_PAPER_MAX_POINTS points and one above the limit
