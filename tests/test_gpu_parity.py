@@ -116,6 +116,15 @@ def test_parity_random_shapes(rv, oracle_mod, case):
             0x7000 + case)
 
 
+def test_parity_many_hypotheses(rv, oracle_mod):
+    # H = 70,000 (hypothesis indexes above 2^16 in the Philox counter and in the
+    # selection key; 274 scoring workgroups per cluster) on a few clusters.
+    rng = np.random.default_rng(77)
+    clusters = [_cluster(rng, n) for n in (2, 40, 130, 700)]
+    th, vd, off = _frame_from_clusters(clusters)
+    _parity(oracle_mod, "H70000", th, vd, off, 70_000, 0.15, 0x70000)
+
+
 def test_parity_row_and_pass_boundaries(rv, oracle_mod):
     rng = np.random.default_rng(77)
     sizes = [2, 3, 63, 64, 65, 127, 128, 129, 1023, 1024, 1025, 1088, 2047, 2048, 2049, 3000]
